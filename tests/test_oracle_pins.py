@@ -1,0 +1,548 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms for
+special scenes, invariants of front-to-back compositing, brute force with exact
+rational arithmetic, quadrature convergence, and finite differences.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.render import RenderOpts
+
+F32 = np.float32
+
+
+def _sp(z):            # softplus, scalar math
+    return math.log1p(math.exp(z)) if z < 30 else z + math.log1p(math.exp(-z))
+
+
+def _sig(z):
+    return 1.0 / (1.0 + math.exp(-z))
+
+
+def _inv_sp(s):        # inverse softplus
+    return math.log(math.expm1(s))
+
+
+def _slab(o, d, lo, hi):
+    """Exact FP64 ray/box interval (world coordinates)."""
+    t0, t1 = -math.inf, math.inf
+    for a in range(3):
+        if d[a] == 0:
+            if not (lo[a] <= o[a] < hi[a]):
+                return None
+            continue
+        ta, tb = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
+        t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
+    t0 = max(t0, 0.0)
+    return (t0, t1) if t0 < t1 else None
+
+
+def _rays_through_box(rng, n, lo, hi, dist=4.0):
+    """FP32 rays from outside aimed at random interior points of the box [lo, hi]."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    tgt = lo + (hi - lo) * rng.uniform(0.15, 0.85, size=(n, 3))
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = tgt - dist * d
+    return o.astype(F32), d.astype(F32)
+
+
+def _lerp_trilinear(vals, x):
+    """Trilinear interpolation by successive lerps (x in [-1,1]^3, corner c = bx + 2by + 4bz)."""
+    f = (np.asarray(x) + 1.0) / 2.0
+    v = np.asarray(vals, float).reshape(2, 2, 2)       # [bz, by, bx]
+    vx = v[:, :, 0] * (1 - f[0]) + v[:, :, 1] * f[0]
+    vy = vx[:, 0] * (1 - f[1]) + vx[:, 1] * f[1]
+    return vy[0] * (1 - f[2]) + vy[1] * f[2]
+
+
+# ---------------------------------------------------------------- P1 empty scene / miss
+def test_p1_empty_scene_and_miss():
+    empty = synth.SceneData(origin=np.zeros(3), root_size=1.0, root_dims=np.array([4, 4, 4]), max_level=1,
+                            voxels=np.zeros((0, 4), np.int32), z_geo=np.zeros((0, 8), F32),
+                            z_rgb=np.zeros((0, 3, 8), F32), z_int=np.zeros((0, 8), F32))
+    ps = oracle.prepare(empty)
+    o, d = synth.random_rays(5, 50, (0, 0, 0), (4, 4, 4))
+    bg = (0.25, 0.5, 0.75)
+    out = oracle.render_rays(ps, o, d, RenderOpts(background=bg))
+    assert np.all(out["rgb"] == np.array(bg)) and np.all(out["depth"] == 0)
+    assert np.all(out["opacity"] == 0) and np.all(out["intensity"] == 0) and np.all(out["n_hits"] == 0)
+    # rays pointing away from a non-empty scene miss everything
+    sc = synth.random_scene(1)
+    ps = oracle.prepare(sc)
+    o = np.tile(np.array([[10.0, 10.0, 10.0]], F32), (20, 1))
+    d = synth.random_rays(6, 20, (0, 0, 0), (1, 1, 1))[1]
+    d = np.abs(d).astype(F32)                      # all components >= 0: away from the scene
+    for r in range(20):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        assert ids.size == 0
+    out = oracle.render_rays(ps, o, d, RenderOpts(background=bg))
+    assert np.all(out["rgb"] == np.array(bg)) and np.all(out["opacity"] == 0)
+
+
+# ---------------------------------------------------------------- P2 constant voxel
+@pytest.mark.parametrize("S", [1, 4, 7])
+def test_p2_constant_voxel_closed_form(S):
+    rng = np.random.default_rng(20 + S)
+    z_s, z_c = 0.75, np.array([0.25, -1.25, 2.0])     # exact in float32
+    sc = synth.single_voxel_scene(np.full(8, z_s), np.repeat(z_c[:, None], 8, 1), np.full(8, -0.375),
+                                  root_size=2.0, origin=(-1.0, -1.0, -1.0))
+    ps = oracle.prepare(sc)
+    sigma, c, ival = _sp(z_s), np.array([_sig(z) for z in z_c]), _sig(-0.375)
+    o, d = _rays_through_box(rng, 40, (-1, -1, -1), (1, 1, 1))
+    bg = np.array([0.1, 0.2, 0.9])
+    for r in range(o.shape[0]):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        ex = _slab(o[r].astype(float), d[r].astype(float), (-1, -1, -1), (1, 1, 1))
+        assert ids.tolist() == [0] and ex is not None
+        assert abs(float(ti[0]) - ex[0]) < 1e-5 and abs(float(to[0]) - ex[1]) < 1e-5
+        L = float(to[0]) - float(ti[0])
+        out = oracle.render_ray(ps, o[r], d[r], RenderOpts(samples=S, background=bg))
+        O = 1.0 - math.exp(-sigma * L)
+        assert abs(out["opacity"] - O) < 1e-12
+        assert np.allclose(out["rgb"], c * O + bg * (1 - O), atol=1e-12, rtol=0)
+        assert abs(out["intensity"] - ival * O) < 1e-12
+        tau = sigma * L / S
+        D = sum(math.exp(-k * tau) * (1 - math.exp(-tau)) * (float(ti[0]) + (k + 0.5) * L / S) for k in range(S))
+        assert abs(out["depth"] - D) < 1e-12
+
+
+# ---------------------------------------------------------------- P3 density linear along x
+def test_p3_linear_density_midpoint_exact():
+    rng = np.random.default_rng(3)
+    a, b = 1.3, 0.9                     # sigma(x) = a + b x_0, positive on [-1, 1]
+    zg = [_inv_sp(a + b * (2 * (c & 1) - 1)) for c in range(8)]
+    sc = synth.single_voxel_scene(zg, np.zeros((3, 8)), None, root_size=1.0, origin=(0.0, 0.0, 0.0))
+    ps = oracle.prepare(sc)
+    s_lo, s_hi = _sp(float(sc.z_geo[0, 0])), _sp(float(sc.z_geo[0, 1]))   # the float32-stored corners
+    a, b = (s_lo + s_hi) / 2, (s_hi - s_lo) / 2
+    o, d = _rays_through_box(rng, 30, (0, 0, 0), (1, 1, 1))
+    for r in range(o.shape[0]):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        L = float(to[0]) - float(ti[0])
+        mid = o[r].astype(float) + 0.5 * (float(ti[0]) + float(to[0])) * d[r].astype(float)
+        sig_mid = a + b * (2.0 * mid[0] - 1.0)
+        for S in (1, 2, 5, 16):
+            out = oracle.render_ray(ps, o[r], d[r], RenderOpts(samples=S))
+            assert abs(out["opacity"] - (1 - math.exp(-L * sig_mid))) < 1e-12
+
+
+def test_p3_colour_corner_order_small_density_limit():
+    # red varies along x, green along y, blue along z; with vanishing density C / O -> c(x_mid)
+    rng = np.random.default_rng(4)
+    zr = np.zeros((3, 8))
+    vals = {0: (0.5, 0.3), 1: (0.5, -0.3), 2: (0.6, 0.2)}   # channel: (mean, slope)
+    for ch, (m, s) in vals.items():
+        for c in range(8):
+            bit = (c >> ch) & 1
+            v = m + s * (2 * bit - 1)
+            zr[ch, c] = math.log(v / (1 - v))
+    sc = synth.single_voxel_scene(np.full(8, _inv_sp(1e-7)), zr, None, root_size=1.0)
+    ps = oracle.prepare(sc)
+    o, d = _rays_through_box(rng, 20, (0, 0, 0), (1, 1, 1))
+    for r in range(o.shape[0]):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        mid = o[r].astype(float) + 0.5 * (float(ti[0]) + float(to[0])) * d[r].astype(float)
+        out = oracle.render_ray(ps, o[r], d[r], RenderOpts(samples=4))
+        want = [vals[ch][0] + vals[ch][1] * (2 * mid[ch] - 1) for ch in range(3)]
+        assert np.allclose(out["rgb"] / out["opacity"], want, atol=1e-6)
+
+
+# ---------------------------------------------------------------- P4 opaque slab
+@pytest.mark.parametrize("S", [1, 4])
+def test_p4_opaque_slab_hit_depth(S):
+    rng = np.random.default_rng(40 + S)
+    sc = synth.slab_scene(8, 8, 1.0, 3000.0, nz=6)      # sigma = 3000 / m, slab z in [0, 1]
+    ps = oracle.prepare(sc)
+    checked = 0
+    for _ in range(200):
+        e = np.array([rng.uniform(1.1, 6.9), rng.uniform(1.1, 6.9), 1.0])
+        d = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), -1.0])
+        d /= np.linalg.norm(d)
+        o = e - rng.uniform(2.0, 4.5) * d
+        o32, d32 = o.astype(F32), d.astype(F32)
+        o64, d64 = o32.astype(float), d32.astype(float)
+        t_hit = (1.0 - o64[2]) / d64[2]
+        p = o64 + t_hit * d64
+        vx, vy = int(math.floor(p[0])), int(math.floor(p[1]))
+        first = _slab(o64, d64, (vx, vy, 0), (vx + 1, vy + 1, 1))
+        if first is None or 3000.0 * (first[1] - first[0]) / S < 30:
+            continue
+        out = oracle.render_ray(ps, o32, d32, RenderOpts(samples=S))
+        d1 = first[1] - first[0]
+        assert abs(out["depth"] - (t_hit + d1 / (2 * S))) < 1e-5
+        assert 1.0 - out["opacity"] < 1e-12
+        # colour = trilinear interpolation of the activated corners at the first sample
+        t1 = t_hit + d1 / (2 * S)
+        x = 2.0 * (o64 + t1 * d64 - np.array([vx, vy, 0.0])) - 1.0
+        v = vx * 8 + vy
+        want = [_lerp_trilinear([_sig(z) for z in sc.z_rgb[v, ch]], x) for ch in range(3)]
+        assert np.allclose(out["rgb"], want, atol=1e-5)
+        checked += 1
+    assert checked > 100
+
+
+# ---------------------------------------------------------------- P5 invariants
+def test_p5_invariants_random_scenes():
+    for seed in (7, 8):
+        sc = synth.random_scene(seed)
+        ps = oracle.prepare(sc)
+        lo = sc.origin
+        hi = sc.origin + sc.root_dims * sc.root_size
+        o, d = synth.random_rays(seed, 150, lo, hi)
+        bg = (0.3, 0.6, 0.1)
+        out = oracle.render_rays(ps, o, d, RenderOpts(background=bg, t_min=0.0))
+        assert all(np.all(np.isfinite(v)) for v in out.values())
+        assert np.all(out["opacity"] >= 0) and np.all(out["opacity"] <= 1)
+        assert np.allclose(out["opacity"], 1 - out["t_end"], atol=0, rtol=0)
+        assert np.all(out["rgb"] >= -1e-15) and np.all(out["rgb"] <= 1 + 1e-15)
+        assert np.all(out["intensity"] >= 0) and np.all(out["intensity"] <= out["opacity"] + 1e-15)
+        for r in range(o.shape[0]):
+            ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+            assert np.all(ti < to)
+            assert np.all(to[:-1] <= ti[1:])                        # disjoint, ascending
+            if ids.size:
+                assert 0 <= out["depth"][r] <= out["opacity"][r] * float(to[-1]) + 1e-12
+            else:
+                assert out["depth"][r] == 0
+        assert np.sum(out["n_hits"]) > 100
+
+
+# ---------------------------------------------------------------- P6 over-operator split
+def test_p6_front_back_split():
+    sc = synth.random_scene(11, root_dims=(6, 4, 4), max_level=2)
+    ps = oracle.prepare(sc)
+    lo, hi = sc.finest_bounds()
+    X = 3 * (1 << sc.max_level)                     # plane on a root-cell boundary
+    front = sc.subset(hi[:, 0] <= X)
+    back = sc.subset(lo[:, 0] >= X)
+    assert front.n + back.n == sc.n and front.n > 10 and back.n > 10
+    o, d = synth.random_rays(12, 150, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    d = d.copy()
+    d[:, 0] = np.abs(d[:, 0])                       # every ray crosses x = X at most once, forward
+    bg = np.array([0.2, 0.4, 0.6])
+    full = oracle.render_rays(ps, o, d, RenderOpts(background=bg, t_min=0.0))
+    f = oracle.render_rays(oracle.prepare(front), o, d, RenderOpts(background=(0, 0, 0), t_min=0.0))
+    b = oracle.render_rays(oracle.prepare(back), o, d, RenderOpts(background=bg, t_min=0.0))
+    Tf = f["t_end"]
+    assert np.allclose(full["rgb"], f["rgb"] + Tf[:, None] * b["rgb"], atol=1e-13, rtol=0)
+    assert np.allclose(full["depth"], f["depth"] + Tf * b["depth"], atol=1e-12, rtol=0)
+    assert np.allclose(full["intensity"], f["intensity"] + Tf * b["intensity"], atol=1e-13, rtol=0)
+    assert np.allclose(full["t_end"], Tf * b["t_end"], atol=1e-14, rtol=0)
+    assert np.sum((f["n_hits"] > 0) & (b["n_hits"] > 0)) > 20
+
+
+# ---------------------------------------------------------------- P7 upload order
+def test_p7_shuffle_only_renames():
+    sc = synth.random_scene(13)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    sp = sc.permuted(perm)
+    o, d = synth.random_rays(14, 60, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    a = oracle.render_rays(oracle.prepare(sc), o, d, RenderOpts())
+    b = oracle.render_rays(oracle.prepare(sp), o, d, RenderOpts())
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    ps_a, ps_b = oracle.prepare(sc), oracle.prepare(sp)
+    for r in range(o.shape[0]):
+        ia, ta, ua = oracle.hit_list(ps_a, o[r], d[r])
+        ib, tb, ub = oracle.hit_list(ps_b, o[r], d[r])
+        assert np.array_equal(ia, perm[ib]) and np.array_equal(ta, tb) and np.array_equal(ua, ub)
+
+
+# ---------------------------------------------------------------- P8 quadrature
+def _gl_integrals(sigma_fn, rgb_fn, t0, t1, n=64):
+    """Continuous volume rendering of one segment by composite Gauss-Legendre quadrature."""
+    xg, wg = np.polynomial.legendre.leggauss(16)
+    edges = np.linspace(t0, t1, n + 1)
+    ts, ws = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        ts.append((a + b) / 2 + (b - a) / 2 * xg)
+        ws.append((b - a) / 2 * wg)
+    ts, ws = np.concatenate(ts), np.concatenate(ws)
+    sig = np.array([sigma_fn(t) for t in ts])
+    # optical depth from t0 to each node, by the same quadrature on [t0, t]
+    tau = np.array([_gl_tau(sigma_fn, t0, t) for t in ts])
+    T = np.exp(-tau)
+    C = np.sum(ws[:, None] * (T * sig)[:, None] * np.array([rgb_fn(t) for t in ts]), axis=0)
+    return 1.0 - math.exp(-_gl_tau(sigma_fn, t0, t1)), C
+
+
+def _gl_tau(sigma_fn, a, b):
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    t = (a + b) / 2 + (b - a) / 2 * xg
+    return float(np.sum((b - a) / 2 * wg * np.array([sigma_fn(x) for x in t])))
+
+
+@pytest.mark.parametrize("field", ["corner", "paper"])
+def test_p8_midpoint_rule_converges_quadratically(field):
+    rng = np.random.default_rng(8)
+    zg = rng.normal(0.5, 0.8, 8)
+    zr = rng.normal(0, 1, (3, 8))
+    if field == "paper":
+        zg = np.array([0.6, -0.4, 0.3, 0.2, 0, 0, 0, 0])
+    sc = synth.single_voxel_scene(zg, zr, None, root_size=2.0, origin=(0.0, 0.0, 0.0))
+    ps = oracle.prepare(sc)
+    o, d = _rays_through_box(rng, 1, (0, 0, 0), (2, 2, 2))
+    o, d = o[0], d[0]
+    ids, ti, to = oracle.hit_list(ps, o, d)
+    t0, t1 = float(ti[0]), float(to[0])
+    o64, d64 = o.astype(float), d.astype(float)
+
+    def xl(t):
+        return (o64 + t * d64) - 1.0            # local coords: (p - 0) * 2 / 2 - 1
+
+    if field == "corner":
+        sp = [_sp(z) for z in zg]
+        sg = [[_sig(z) for z in zr[ch]] for ch in range(3)]
+        sigma_fn = lambda t: _lerp_trilinear(sp, xl(t))
+        rgb_fn = lambda t: np.array([_lerp_trilinear(sg[ch], xl(t)) for ch in range(3)])
+    else:
+        sigma_fn = lambda t: math.exp(float(np.dot(zg[:3], xl(t)) + zg[3]))
+        C0, C1 = 0.28209479177387814, 0.4886025119029199
+        gam = np.array([C0, C1 * d64[0], C1 * d64[1], C1 * d64[2]])
+        rgb_fn = lambda t: np.array([_sig(float(np.dot(zr[ch, :3], xl(t)) + np.dot(zr[ch, 3:7], gam)))
+                                     for ch in range(3)])
+    O_ex, C_ex = _gl_integrals(sigma_fn, rgb_fn, t0, t1)
+    errO, errC = [], []
+    for S in (4, 8, 16, 32):
+        out = oracle.render_ray(ps, o, d, RenderOpts(samples=S, t_min=0.0, field=field))
+        errO.append(abs(out["opacity"] - O_ex))
+        errC.append(np.max(np.abs(out["rgb"] - C_ex)))
+    for e in (errO, errC):
+        ratios = [e[i] / e[i + 1] for i in range(len(e) - 1)]
+        assert all(3.3 < q < 4.7 for q in ratios), ratios
+
+
+def test_p8_single_sample_is_the_paper_rule():
+    """S = 1: alpha_i = 1 - exp(-sigma(mid_i) delta_i), C = sum_i prod_{j<i}(1 - alpha_j) alpha_i c(mid_i)."""
+    sc = synth.random_scene(15)
+    ps = oracle.prepare(sc)
+    o, d = synth.random_rays(16, 40, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    lo_i, hi_i = sc.finest_bounds()
+    s_k = sc.root_size / (1 << sc.max_level)
+    for r in range(o.shape[0]):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        alphas, cols = [], []
+        for v, a, b in zip(ids, ti, to):
+            a, b = float(a), float(b)
+            mid = o[r].astype(float) + 0.5 * (a + b) * d[r].astype(float)
+            lo_w = sc.origin + lo_i[v] * s_k
+            hi_w = sc.origin + hi_i[v] * s_k
+            x = np.clip(2 * (mid - lo_w) / (hi_w - lo_w) - 1, -1, 1)
+            sig = _lerp_trilinear([_sp(z) for z in sc.z_geo[v]], x)
+            alphas.append(1 - math.exp(-sig * (b - a)))
+            cols.append([_lerp_trilinear([_sig(z) for z in sc.z_rgb[v, ch]], x) for ch in range(3)])
+        C = np.zeros(3)
+        for i in range(len(alphas)):
+            C += np.prod([1 - alphas[j] for j in range(i)]) * alphas[i] * np.array(cols[i])
+        out = oracle.render_ray(ps, o[r], d[r], RenderOpts(samples=1, t_min=0.0))
+        assert np.allclose(out["rgb"], C, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P9 exact rational hits
+def _exact_interval(o, d, org, gs, lo, hi):
+    og = [(Fraction(float(o[a])) - Fraction(float(org[a]))) * gs for a in range(3)]
+    dg = [Fraction(float(d[a])) * gs for a in range(3)]
+    t0, t1 = Fraction(0), None
+    for a in range(3):
+        if dg[a] == 0:
+            if not (lo[a] <= og[a] < hi[a]):
+                return None, None
+            continue
+        ta, tb = (lo[a] - og[a]) / dg[a], (hi[a] - og[a]) / dg[a]
+        t0 = max(t0, min(ta, tb))
+        t1 = max(ta, tb) if t1 is None else min(t1, max(ta, tb))
+    return t0, t1
+
+
+def test_p9_fp32_hits_vs_exact_rationals():
+    sc = synth.random_scene(17, root_dims=(4, 3, 3), max_level=2)
+    ps = oracle.prepare(sc)
+    gs = Fraction(1 << sc.max_level) / Fraction(sc.root_size)
+    lo_i, hi_i = sc.finest_bounds()
+    o, d = synth.random_rays(18, 60, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    # a few axis-parallel rays exercise the parallel-axis rule
+    d[:6] = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0], [0, 0, -1]], F32)
+    margin = Fraction(1, 10 ** 5) * gs                      # 1e-5 m in grid units
+    n_deg = n_pairs = 0
+    for r in range(o.shape[0]):
+        ids, ti, to = oracle.hit_list(ps, o[r], d[r])
+        got = {int(v): (float(a), float(b)) for v, a, b in zip(ids, ti, to)}
+        dn = max(abs(Fraction(float(x))) for x in d[r]) * gs
+        for v in range(sc.n):
+            n_pairs += 1
+            e0, e1 = _exact_interval(o[r], d[r], sc.origin.astype(F32), gs, lo_i[v], hi_i[v])
+            if e0 is None:
+                assert v not in got
+                continue
+            slack = (e1 - e0) * dn
+            if slack > margin:
+                assert v in got
+                assert abs(got[v][0] - float(e0)) <= 1e-5 + 1e-6 * abs(float(e0))
+                assert abs(got[v][1] - float(e1)) <= 1e-5 + 1e-6 * abs(float(e1))
+            elif slack < -margin:
+                assert v not in got
+            else:
+                n_deg += 1
+    assert n_deg <= 0.01 * n_pairs
+
+
+# ---------------------------------------------------------------- P10 sensor closed forms
+def test_p10_pinhole_reprojects_to_its_pixel():
+    R0 = synth.look_at((3, -4, 2), (0, 0, 0))
+    s = synth.pinhole(33, 21, 70.0, R0, (3, -4, 2))
+    o, d, t, valid = oracle.sensor_rays(s)
+    assert np.all(valid) and np.allclose(np.linalg.norm(d, axis=1), 1, atol=1e-14)
+    dc = d @ R0                                 # camera-frame directions (R0 orthonormal)
+    u = s["fx"] * dc[:, 0] / dc[:, 2] + s["cx"] - 0.5
+    v = s["fy"] * dc[:, 1] / dc[:, 2] + s["cy"] - 0.5
+    uu, vv = np.meshgrid(np.arange(33), np.arange(21))
+    assert np.allclose(u, uu.ravel(), atol=1e-9) and np.allclose(v, vv.ravel(), atol=1e-9)
+    centre = 10 * 33 + 16                        # odd sizes: the principal point is a pixel centre
+    assert np.allclose(d[centre], R0[:, 2], atol=1e-15)
+    assert np.allclose(o, np.array([3, -4, 2.0]))
+
+
+def test_p10_fisheye_equidistant():
+    R0 = synth.yaw_pitch_camera(30.0, 10.0)
+    s = synth.fisheye_equidistant(96, 72, 190.0, R0, (1, 2, 3))
+    o, d, t, valid = oracle.sensor_rays(s)
+    dc = d @ R0
+    uu, vv = np.meshgrid(np.arange(96) + 0.5, np.arange(72) + 0.5)
+    x, y = (uu.ravel() - s["cx"]), (vv.ravel() - s["cy"])
+    r = np.hypot(x, y)
+    theta = np.arccos(np.clip(dc[:, 2], -1, 1))
+    assert np.all(valid == (r / s["fx"] <= s["max_theta"]))
+    assert np.allclose(theta[valid], (r / s["fx"])[valid], atol=1e-12)
+    assert np.allclose(np.arctan2(dc[valid, 1], dc[valid, 0]), np.arctan2(y, x)[valid], atol=1e-12)
+    # the 90-degree circle has radius f pi / 2
+    ring = valid & (np.abs(r - s["fx"] * math.pi / 2) < 0.5)
+    assert np.any(ring) and np.all(np.abs(dc[ring, 2]) < 0.5 / s["fx"] + 1e-12)
+    assert np.all(d[~valid] == 0)
+    # 190 deg spans the width: f = (W / 2) / (95 deg)
+    assert abs(s["fx"] - 48 / math.radians(95)) < 1e-12
+
+
+def test_p10_lidar_angles_and_rolling_shutter():
+    s = synth.lidar_spinning(16, 64, -25.0, 15.0, np.eye(3), (1, 2, 3), 0.1, v=(10, 0, 0), w=(0, 0, 0.5))
+    o, d, t, valid = oracle.sensor_rays(s)
+    B, J = 16, 64
+    b, j = np.divmod(np.arange(B * J), J)
+    elev = np.radians(-25 + 40 * b / (B - 1))
+    tj = 0.1 * j / J
+    az = 2 * math.pi * (j + 0.5) / J + 0.5 * tj         # spin about +z adds w t
+    assert np.allclose(np.arcsin(np.clip(d[:, 2], -1, 1)), elev, atol=1e-12)
+    dazi = np.angle(np.exp(1j * (np.arctan2(d[:, 1], d[:, 0]) - az)))
+    assert np.allclose(dazi, 0, atol=1e-12)
+    assert np.allclose(t, tj) and np.allclose(o, np.array([1, 2, 3]) + np.outer(tj, [10, 0, 0]))
+    # no motion: rolling shutter equals the global shutter bit for bit
+    s0 = synth.lidar_spinning(16, 64, -25.0, 15.0, np.eye(3), (1, 2, 3), 0.1)
+    g = dict(s0, dt_line=0.0)
+    a1, a2 = oracle.sensor_rays(s0), oracle.sensor_rays(g)
+    assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
+
+
+def test_p10_camera_rolling_shutter_rows():
+    R0 = synth.yaw_pitch_camera(0, 0)
+    s = synth.pinhole(8, 6, 60.0, R0, (0, 0, 1), t0=0.5, dt_line=30e-6, v=(10, 0, 0), w=(0, 0, 2.0))
+    o, d, t, valid = oracle.sensor_rays(s)
+    rows = np.arange(48) // 8
+    assert np.allclose(t, 0.5 + rows * 30e-6)
+    assert np.allclose(o, np.array([0, 0, 1.0]) + np.outer(rows * 30e-6, [10, 0, 0]))
+    g = oracle.sensor_rays(dict(s, dt_line=0.0))
+    # the yaw rate turns row r's rays by 2 * r * 30e-6 rad about +z relative to the global shutter
+    ang = np.arctan2(d[:, 1], d[:, 0]) - np.arctan2(g[1][:, 1], g[1][:, 0])
+    assert np.allclose(ang, 2.0 * rows * 30e-6, atol=1e-12)
+
+
+def test_sh_basis_is_orthonormal():
+    # Monte Carlo-free: exact spherical quadrature (Gauss-Legendre in cos theta x uniform phi)
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    G = np.zeros((4, 4))
+    for ct, w in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(nphi):
+            ph = 2 * math.pi * k / nphi
+            g = oracle.sh_basis([st * math.cos(ph), st * math.sin(ph), ct])
+            G += w * (2 * math.pi / nphi) * np.outer(g, g)
+    assert np.allclose(G, np.eye(4), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P11 gradient vs FD
+def test_p11_oracle_gradient_matches_central_differences():
+    sc = synth.random_scene(21, root_dims=(3, 3, 3), max_level=1, fill=0.7)
+    o, d = synth.random_rays(22, 24, sc.origin, sc.origin + sc.root_dims * sc.root_size, inside_frac=0.0)
+    rng = np.random.default_rng(23)
+    n = o.shape[0]
+    g_rgb, g_d, g_o, g_i = rng.normal(size=(n, 3)), rng.normal(size=n), rng.normal(size=n), rng.normal(size=n)
+    opts = RenderOpts(samples=3, t_min=0.0, background=(0.1, 0.2, 0.3))
+    # the FD runs in float64 end to end: parameters are perturbed as float64 copies
+    sc64 = synth.SceneData(**{**sc.__dict__, "z_geo": sc.z_geo.astype(np.float64),
+                              "z_rgb": sc.z_rgb.astype(np.float64), "z_int": sc.z_int.astype(np.float64)})
+
+    def loss(s):
+        out = oracle.render_rays(oracle.prepare(s), o, d, opts)
+        return float(np.sum(g_rgb * out["rgb"]) + g_d @ out["depth"] + g_o @ out["opacity"] + g_i @ out["intensity"])
+
+    dg, dr, di = oracle.grad_rays(oracle.prepare(sc64), o, d, opts, g_rgb, g_d, g_o, g_i)
+    touched = np.nonzero(np.any(dg != 0, axis=1))[0]
+    assert touched.size > 5
+    eps = 1e-6
+    for name, arr, grad in (("z_geo", sc64.z_geo, dg), ("z_rgb", sc64.z_rgb, dr), ("z_int", sc64.z_int, di)):
+        for _ in range(8):
+            v = int(rng.choice(touched))
+            idx = (v,) + tuple(int(rng.integers(0, s)) for s in arr.shape[1:])
+            old = arr[idx]
+            arr[idx] = old + eps
+            lp = loss(sc64)
+            arr[idx] = old - eps
+            lm = loss(sc64)
+            arr[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
+
+
+# ---------------------------------------------------------------- early termination
+def test_early_termination_after_the_voxel_that_crosses_t_min():
+    # two voxels in a row along x; the first is nearly opaque (optical depth ~ 30 along x)
+    zg = np.array([[30.0] * 8, [0.5] * 8], F32)
+    sc = synth.SceneData(origin=np.zeros(3), root_size=1.0, root_dims=np.array([2, 1, 1]), max_level=0,
+                         voxels=np.array([[0, 0, 0, 0], [0, 1, 0, 0]], np.int32), z_geo=zg,
+                         z_rgb=np.zeros((2, 3, 8), F32), z_int=np.zeros((2, 8), F32))
+    ps = oracle.prepare(sc)
+    o = np.array([-1.0, 0.5, 0.5], F32)
+    d = np.array([1.0, 0.0, 0.0], F32)
+    stop = oracle.render_ray(ps, o, d, RenderOpts(t_min=1e-6))
+    full = oracle.render_ray(ps, o, d, RenderOpts(t_min=0.0))
+    assert stop["n_hits"] == 1 and full["n_hits"] == 2
+    assert stop["t_end"] < 1e-6 and full["t_end"] < stop["t_end"]
+    # a threshold below the first voxel's transmittance lets the ray continue
+    cont = oracle.render_ray(ps, o, d, RenderOpts(t_min=0.5 * stop["t_end"]))
+    assert cont["n_hits"] == 2
+
+
+# ---------------------------------------------------------------- rays lying on voxel faces
+def test_axis_parallel_rays_on_faces_use_half_open_slabs():
+    # a dense 4x4x4 block: a ray along +x lying exactly on a y (and z) face plane belongs to
+    # the cells above the plane only, so its hits partition the block's x extent
+    vox = np.array([[0, i, j, k] for k in range(4) for j in range(4) for i in range(4)], np.int32)
+    n = vox.shape[0]
+    sc = synth.SceneData(origin=np.zeros(3), root_size=1.0, root_dims=np.array([4, 4, 4]), max_level=0,
+                         voxels=vox, z_geo=np.zeros((n, 8), F32), z_rgb=np.zeros((n, 3, 8), F32))
+    ps = oracle.prepare(sc)
+    for y, z in ((1.0, 2.0), (0.0, 0.5), (3.0, 3.0), (2.5, 1.0)):
+        ids, ti, to = oracle.hit_list(ps, np.array([-2.0, y, z], F32), np.array([1.0, 0.0, 0.0], F32))
+        assert ids.size == 4
+        assert np.all(vox[ids, 1] == np.arange(4))
+        assert np.all(vox[ids, 2] == int(y)) and np.all(vox[ids, 3] == int(z))
+        assert np.array_equal(to[:-1], ti[1:])
+    # on the grid's top face the ray is outside every cell
+    ids, _, _ = oracle.hit_list(ps, np.array([-2.0, 4.0, 1.0], F32), np.array([1.0, 0.0, 0.0], F32))
+    assert ids.size == 0
