@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the sparse-local-field ray-casting renderer on one MI355X.
+
+One step = one 1920x1080 pinhole camera frame plus one 64 x 2,048 rolling-shutter LiDAR sweep
+(10 m/s) rendered from the ~2M-voxel driving scene (5 levels, 1.6 m to 0.1 m), S = 4 samples per
+voxel, t_min = 1e-6.  The scene is resident in HBM before timing; ray generation is fused into the
+render kernels.  Prints one JSON line:
+  value      camera + LiDAR rays per second (Mrays/s) over the timed steps
+  roofline   the camera render kernel (the dominant kernel): algorithmic bytes per launch
+             (128 B per shaded voxel hit: density + RGB corner records, plus 20 B of outputs per
+             ray) over its average duration, against the 8 TB/s HBM peak
+  cpu_baseline  the CPU oracle on a bounded sample of the same rays, over a process pool
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CAM_HIT_BYTES, CAM_RAY_BYTES = 128, 20     # sigma + RGB corner logits (32 floats); rgb, depth, opacity
+LID_HIT_BYTES, LID_RAY_BYTES = 64, 12      # sigma + intensity corner logits (16 floats); depth, intensity, opacity
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_render_camera_driving.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_18713_amd", "csrc", f) for f in ("device.hpp", "render.hip")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_rays: int):
+    """HBM bytes per camera launch from the committed rocprofv3 counter summary, or None when the
+    counters were taken on other kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("rays_per_launch") != launch_rays:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------------ CPU baseline (oracle)
+_W = {}
+
+
+def _worker_init():
+    import oracle
+    import synth
+    data = synth.config1_scene()
+    _W["ps"] = oracle.prepare(data)
+
+
+def _worker_render(args):
+    import oracle
+    o, d = args
+    t0 = time.perf_counter()
+    oracle.render_rays(_W["ps"], o, d, oracle.RenderOpts(samples=4, t_min=1e-6))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_cam=480, n_lid=32, seed=5):
+    """Oracle rays/s on a bounded sample (camera and LiDAR rays in the step's proportion)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    import synth
+    rng = np.random.default_rng(seed)
+    oc, dc, _, _ = oracle.sensor_rays(synth.config1_camera())
+    ol, dl, _, _ = oracle.sensor_rays(synth.config2_lidar())
+    ic = rng.choice(oc.shape[0], n_cam, replace=False)
+    il = rng.choice(ol.shape[0], n_lid, replace=False)
+    o = np.concatenate([oc[ic], ol[il]]).astype(np.float32)
+    d = np.concatenate([dc[ic], dl[il]]).astype(np.float32)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    chunks = [(o[i::workers * 4], d[i::workers * 4]) for i in range(workers * 4)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_worker_init) as pool:
+        pool.map(_worker_render, [(o[:1], d[:1])] * workers)       # warm every worker
+        t0 = time.perf_counter()
+        cpu_s = sum(pool.map(_worker_render, chunks))
+        wall = time.perf_counter() - t0
+    n = o.shape[0]
+    return {"value": n / wall / 1e6, "unit": "Mrays/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_cam} pixels of the 1920x1080 camera + {n_lid} rays of the LiDAR sweep (seed {seed}) "
+                      f"against all voxels of the driving scene; {cpu_s:.1f} CPU-s in {wall:.1f} s wall"}
+
+
+# ------------------------------------------------------------------ GPU
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path runs on a single "
+              f"GPU; sharding across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_18713_amd as salf
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    data = synth.config1_scene()
+    t_gen = time.perf_counter() - t0
+    scene = salf.Scene.from_data(data, device=dev)
+    torch.cuda.synchronize()
+    # scene build time alone (upload excluded)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    scene2 = salf.Scene(scene._voxels, scene.geo, scene.rgb, scene.intensity, data.origin, data.root_size,
+                        data.root_dims, data.max_level)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    scene2.destroy()
+    del scene2
+
+    cam = synth.config1_camera()
+    lid = synth.config2_lidar()
+    n_cam, n_lid = cam["width"] * cam["height"], lid["width"] * lid["height"]
+    opts = dict(samples=4, t_min=1e-6)
+    cam_out = {"rgb": torch.empty((n_cam, 3), device=dev), "depth": torch.empty(n_cam, device=dev),
+               "opacity": torch.empty(n_cam, device=dev)}
+    lid_out = {k: torch.empty(n_lid, device=dev) for k in ("depth", "intensity", "opacity")}
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        salf.render(scene, sensor=cam, outputs=cam_out.keys(), out=cam_out, **opts)
+        if ev is not None:
+            ev[1].record()
+        salf.render(scene, sensor=lid, outputs=lid_out.keys(), out=lid_out, **opts)
+        if ev is not None:
+            ev[2].record()
+
+    # instrumented run (not timed): shaded hits per ray for the algorithmic byte count
+    hc = salf.render(scene, sensor=cam, outputs=("n_hits",), **opts)["n_hits"]
+    hl = salf.render(scene, sensor=lid, outputs=("n_hits",), **opts)["n_hits"]
+    hits_cam, hits_lid = int(hc.sum().item()), int(hl.sum().item())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    cam_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    lid_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    step_ms = sum(e[0].elapsed_time(e[2]) for e in evs) / args.steps
+    rays = n_cam + n_lid
+    value = rays / (wall / args.steps) / 1e6
+
+    cam_bytes = hits_cam * CAM_HIT_BYTES + n_cam * CAM_RAY_BYTES
+    lid_bytes = hits_lid * LID_HIT_BYTES + n_lid * LID_RAY_BYTES
+    achieved = cam_bytes / (cam_ms * 1e-3) / 1e9
+    traffic = measured_traffic(n_cam)
+    rec = {
+        "metric": "Mrays/s camera+LiDAR render on 1 GPU",
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "driving scene (2.01M voxels, 5 levels 1.6-0.1 m) + 1920x1080 pinhole frame + "
+                        "64x2048 rolling-shutter LiDAR sweep, S=4, t_min=1e-6",
+            "n_voxels": int(data.n), "camera_rays": n_cam, "lidar_rays": n_lid, "samples_per_voxel": 4,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "render_kernel<corner, rgb> (camera frame)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "camera": {"ms": round(cam_ms, 4), "mrays_s": round(n_cam / cam_ms / 1e3, 2),
+                   "shaded_hits_per_ray": round(hits_cam / n_cam, 3), "algorithmic_bytes": cam_bytes},
+        "lidar": {"ms": round(lid_ms, 4), "mrays_s": round(n_lid / lid_ms / 1e3, 2),
+                  "shaded_hits_per_ray": round(hits_lid / n_lid, 3), "algorithmic_bytes": lid_bytes,
+                  "achieved_GBs": round(lid_bytes / (lid_ms * 1e-3) / 1e9, 1),
+                  "sweeps_per_s": round(1e3 / lid_ms, 1)},
+        "event_ms_per_step": round(step_ms, 4),
+        "scene_build_ms": round(build_ms, 3),
+        "scene_generate_s": round(t_gen, 2),
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

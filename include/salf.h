@@ -1,0 +1,285 @@
+/*
+ * salf.h - C ABI of the sparse-local-field ray-casting renderer for AMD Instinct MI355X (gfx950).
+ *
+ * The renderer implements the ray-casting mode of "SaLF: Sparse Local Fields for Multi-Sensor
+ * Rendering in Real-Time" (arXiv 2507.18713):
+ *   - a scene is a sparse set of non-overlapping cubic voxels on an adaptive grid: a regular root
+ *     grid of edge s0 whose cells subdivide 8-way up to K levels, only non-empty voxels stored
+ *     (Sec. 3.1 "Representation");
+ *   - each voxel is a local field giving density and colour at normalized local coordinates
+ *     x in [-1, 1]^3 (Sec. 3.1, Eq. 1-2);
+ *   - a ray visits the occupied voxels it crosses front to back through an octree that skips
+ *     empty space (Sec. 3.2, "Ray-Casting with Octree Acceleration"), samples each ray-voxel
+ *     segment at midpoints and alpha-composites with alpha = 1 - exp(-sigma delta) (Eq. 3-4);
+ *   - rays come from sensor intrinsics and extrinsics (Sec. 1), including fisheye cameras and
+ *     camera and LiDAR rolling shutter (Sec. 5.3), and spinning LiDAR with intensity and an
+ *     opacity used for ray drop (Sec. 5.3, Table III);
+ *   - training needs the gradient of the rendered outputs (Sec. 4.2, Eq. 7).
+ *
+ * Conventions for every call
+ *   - Every entry point returns salf_status: SALF_OK (0) or a negative error code.  The message
+ *     of the last failure on the calling thread is returned by salf_last_error().  No C++
+ *     exception crosses this interface.
+ *   - GPU work is enqueued asynchronously on the caller's HIP stream (`void* stream` is a
+ *     hipStream_t; NULL is the default stream).  Results are valid once that stream has
+ *     synchronized.  Faults raised while kernels run surface at the next salf_sync().
+ *   - Memory: every device buffer is owned by the caller (for example a torch tensor).  The
+ *     library never frees caller memory and allocates no device memory of its own: internal
+ *     structures live in caller-provided workspaces whose size is given by *_workspace_size().
+ *     Device pointers must belong to the context's device and be 16-byte aligned.
+ *   - Host structs passed by pointer are read during the call only.
+ *
+ * Geometry and units
+ *   - World frame: metres, z up.  The scene grid spans origin + [0, root_dims * s0) per axis.
+ *   - A voxel is (l, i, j, k): level l in [0, K] (0 = root cells of edge s0, K = finest edge
+ *     s_K = s0 / 2^K) and integer coordinates in units of s_l = s0 / 2^l.
+ *   - Finest-grid frame ("grid frame"): g = (p - org) * gs with gs = 2^K / s0.  The FP32 rule
+ *     that decides which voxels a ray hits is, with every operation rounded to nearest even:
+ *       org32 = (float)origin, gs32 = (float)((double)(1 << K) / s0),
+ *       og = (o - org32) * gs32, dg = d * gs32, inv = 1 / dg   (per axis, FP32)
+ *       an axis is parallel when dg == 0 or inv is infinite; for a parallel axis the voxel's
+ *       slab is all t when lo <= og < hi and empty otherwise; for other axes it is
+ *       [min(tlo, thi), max(tlo, thi)] with t = (P - og) * inv for the planes P = lo, hi
+ *       (lo, hi = the voxel's integer bounds in finest cells);
+ *       t_in = max(t_near, slab starts) (a zero t_in is +0), t_out = min(t_far, slab ends);
+ *       the ray hits the voxel iff t_in < t_out.
+ *     A ray with a non-finite component or with all three axes parallel hits nothing.
+ *     Hits are ordered by t_in, which is strictly increasing along a ray.
+ *   - Samples: each hit segment [t_in, t_out] is cut into S equal pieces sampled at their
+ *     midpoints t_k = t_in + (k + 1/2) (t_out - t_in) / S; S = 1 is the paper's single
+ *     midpoint per segment (Sec. 3.1, after Eq. 4).  Each piece is one compositing step.
+ *
+ * Parameter buffers (FP32, borrowed by a scene; they must outlive it and may be updated in
+ * place between renders):
+ *   geo [N, 8], rgb [N, 3, 8] (channel-major), intensity [N, 8]   (row = voxel id = upload index)
+ *   SALF_FIELD_CORNER: raw logits at the 8 corners c = bx + 2 by + 4 bz (b = 0 on an axis's low
+ *     face); density corners are softplus(z), colour and intensity corners sigmoid(z), and the
+ *     activated corners are trilinearly interpolated at x.
+ *   SALF_FIELD_PAPER (Eq. 1-2): sigma = exp(geo[0:4] . [x, 1]); colour channel ch =
+ *     sigmoid(rgb[ch][0:3] . x + rgb[ch][3:7] . gamma(omega)) with the real spherical-harmonic
+ *     basis gamma(omega) = (C0, C1 wx, C1 wy, C1 wz), C0 = 1/(2 sqrt(pi)), C1 = sqrt(3)/(2 sqrt(pi)),
+ *     omega = the ray direction; intensity = sigmoid(intensity[0:4] . [x, 1]).  Unused entries of
+ *     each 8-float row are ignored.
+ */
+#ifndef SALF_H
+#define SALF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SALF_ABI_VERSION 1
+
+typedef int32_t salf_status;
+enum {
+  SALF_OK = 0,
+  SALF_ERR_INVALID_ARG = -1,   /* a pointer, size, enum or geometry argument is invalid           */
+  SALF_ERR_OUT_OF_MEMORY = -2, /* a caller-provided workspace is too small                          */
+  SALF_ERR_DEVICE = -3,        /* a HIP call failed (launch error or a fault surfaced at sync)      */
+  SALF_ERR_NOT_FOUND = -4,     /* unknown scene id or ticket                                        */
+  SALF_ERR_BUDGET = -5,        /* a serving request alone exceeds the server's memory budget        */
+  SALF_ERR_BUSY = -6,          /* the object still has work in flight                               */
+  SALF_ERR_UNSUPPORTED = -7    /* a valid but unimplemented combination                             */
+};
+
+enum { SALF_FIELD_CORNER = 0, SALF_FIELD_PAPER = 1 };
+enum { SALF_PINHOLE = 0, SALF_FISHEYE_EQUIDISTANT = 1, SALF_LIDAR_SPINNING = 2 };
+
+#define SALF_MAX_LEVEL 8         /* K <= 8                                                         */
+#define SALF_MAX_SAMPLES 32      /* S <= 32                                                        */
+#define SALF_MAX_FINE_CELLS (1 << 20) /* root_dims[a] << K must stay below this, per axis           */
+
+typedef struct salf_context salf_context;
+
+/* ------------------------------------------------------------------ library and context */
+
+/* SALF_ABI_VERSION of the loaded library. */
+int32_t salf_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer stays valid until
+ * the next failing call on the same thread. */
+const char* salf_last_error(void);
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the handle.
+ * Errors: INVALID_ARG (bad device or NULL out), DEVICE. */
+salf_status salf_create(int32_t hip_device, salf_context** out);
+
+/* Destroy a context and forget its scenes (their workspaces stay owned by the caller).
+ * Errors: INVALID_ARG. */
+salf_status salf_destroy(salf_context* ctx);
+
+/* Synchronize `stream` and report any fault raised by kernels enqueued on it. Errors: DEVICE. */
+salf_status salf_sync(salf_context* ctx, void* stream);
+
+/* ------------------------------------------------------------------ scenes (Sec. 3.1, 3.2) */
+
+typedef struct {
+  double origin[3];      /* world position of the grid's min corner (m)                             */
+  double root_size;      /* s0, edge of a root cell (m), > 0                                         */
+  int32_t root_dims[3];  /* root cells per axis, >= 1                                                */
+  int32_t max_level;     /* K in [0, SALF_MAX_LEVEL]                                                 */
+  int32_t field;         /* SALF_FIELD_CORNER or SALF_FIELD_PAPER                                    */
+  int32_t reserved;      /* must be 0                                                                */
+} salf_scene_desc;
+
+typedef struct {
+  int64_t n_voxels;
+  int64_t n_nodes;          /* internal octree nodes built                                          */
+  int64_t n_root_cells;     /* root_dims product                                                    */
+  int64_t n_occupied_roots; /* root cells holding a voxel or a node                                 */
+  size_t workspace_bytes;   /* bytes of the workspace in use                                        */
+} salf_scene_stats;
+
+/* Bytes of device workspace salf_scene_create needs for `n_voxels` voxels under `desc`.
+ * Errors: INVALID_ARG (bad desc, n_voxels < 0 or > 2^30). */
+salf_status salf_scene_workspace_size(const salf_scene_desc* desc, int64_t n_voxels, size_t* bytes);
+
+/* Build the acceleration structure (a dense root grid whose cells point to 8-ary octrees whose
+ * leaves are empty or hold one voxel, Sec. 3.2) on the GPU and register the scene.
+ *   d_voxels   device int32 [n_voxels, 4] = (l, i, j, k), read during the call only
+ *   d_geo      device float [n_voxels, 8]       borrowed (required)
+ *   d_rgb      device float [n_voxels, 3, 8]    borrowed (NULL: the scene has no colour)
+ *   d_int      device float [n_voxels, 8]       borrowed (NULL: the scene has no intensity)
+ *              (a channel is present iff its pointer is non-NULL; with n_voxels == 0 the buffers
+ *              are never read, but a non-NULL pointer still declares the channel)
+ *   d_workspace, ws_bytes   caller memory of at least salf_scene_workspace_size() bytes; it
+ *              holds the structure for the scene's lifetime and must not be touched meanwhile
+ *   *scene_id  receives the new scene's id
+ * The call blocks until the build has finished on `stream`, so that validation errors can be
+ * returned.  Errors: INVALID_ARG (bad desc; a voxel with a level outside [0, K] or coordinates
+ * outside the grid; two voxels that overlap or repeat; the message names the first offending
+ * voxel index), OUT_OF_MEMORY (ws_bytes too small), DEVICE. */
+salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, int64_t n_voxels,
+                              const int32_t* d_voxels, const float* d_geo, const float* d_rgb,
+                              const float* d_int, void* d_workspace, size_t ws_bytes, void* stream,
+                              int32_t* scene_id);
+
+/* Statistics of a built scene.  Errors: NOT_FOUND. */
+salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out);
+
+/* Forget a scene.  Its workspace and parameter buffers may be freed by the caller once the
+ * work that used them has completed.  Errors: NOT_FOUND. */
+salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id);
+
+/* ------------------------------------------------------------------ sensors (Sec. 1, 5.3) */
+
+typedef struct {
+  int32_t model;        /* SALF_PINHOLE | SALF_FISHEYE_EQUIDISTANT | SALF_LIDAR_SPINNING          */
+  int32_t width;        /* camera: pixels per row; LiDAR: azimuth steps per sweep (columns)       */
+  int32_t height;       /* camera: rows; LiDAR: beams                                              */
+  float fx, fy, cx, cy; /* pinhole focal lengths / principal point (px); fisheye: f = fx            */
+  float max_theta;      /* fisheye: rays with angle > max_theta from the axis are invalid (rad)   */
+  float elev_min, elev_max; /* LiDAR: elevation of beam 0 and of beam height-1 (rad)              */
+  float az0;            /* LiDAR: azimuth offset (rad)                                             */
+  float t0;             /* time of camera row 0 / LiDAR column 0 (s)                              */
+  float dt_line;        /* rolling shutter: time per camera row / LiDAR column (s); 0 = global   */
+  float R0[9];          /* sensor-to-world rotation at t0, row-major                              */
+  float p0[3];          /* sensor position at t0 (m)                                              */
+  float v[3];           /* constant linear velocity (m/s, world)                                  */
+  float w[3];           /* constant angular velocity (rad/s, world)                               */
+  float t_near, t_far;  /* ray extent (m); 0 <= t_near < t_far; t_far may be +inf                 */
+} salf_sensor;
+/* Rays (float32, in this order of operations):
+ *   pose at time t: p(t) = p0 + v (t - t0), R(t) = Exp([w]x (t - t0)) R0; camera row r is
+ *   exposed at t0 + r dt_line, LiDAR column j fires at t0 + j dt_line (all beams together).
+ *   pinhole pixel (u, r): d_cam = normalize((u + 1/2 - cx) / fx, (r + 1/2 - cy) / fy, 1)
+ *   fisheye (equidistant, r = f theta): x = (u + 1/2 - cx) / f, y = (r + 1/2 - cy) / f,
+ *     theta = |(x, y)|, d_cam = (sin theta * x / theta, sin theta * y / theta, cos theta),
+ *     valid iff theta <= max_theta; invalid rays render the background with zero opacity
+ *   LiDAR beam b, column j: e = elev_min + (elev_max - elev_min) b / (height - 1),
+ *     a = az0 + 2 pi (j + 1/2) / width, d_s = (cos e cos a, cos e sin a, sin e)
+ *   camera frame: x right, y down, z forward; LiDAR frame: x forward, y left, z up
+ *   o = p(t), d = R(t) d_cam.  Ray index: camera r * width + u; LiDAR b * width + j. */
+
+/* Number of rays of a sensor (width * height).  Errors: INVALID_ARG. */
+salf_status salf_sensor_ray_count(const salf_sensor* sensor, int64_t* n_rays);
+
+/* Materialize a sensor's rays: d_o, d_d float [n, 3], d_t float [n] (exposure time),
+ * d_valid uint8 [n]; any of the four may be NULL.  Errors: INVALID_ARG, DEVICE. */
+salf_status salf_generate_rays(salf_context* ctx, const salf_sensor* sensor, float* d_o, float* d_d,
+                               float* d_t, uint8_t* d_valid, void* stream);
+
+/* ------------------------------------------------------------------ rendering (Eq. 1-4) */
+
+/* Explicit rays: device float [n, 3] origins and directions (unit length expected; depth is
+ * measured in units of |d|).  All rays share [t_near, t_far].  image_width > 0 declares that the
+ * rays form an image, row-major with that many rays per row (the last row may be short); the
+ * renderer then gives each wave an 8x8 tile of them, exactly as for a sensor.  0 = no layout. */
+typedef struct {
+  const float* o;
+  const float* d;
+  int64_t n;
+  float t_near, t_far;
+  int32_t image_width;
+  int32_t reserved;      /* must be 0 */
+} salf_rays;
+
+typedef struct {
+  int32_t samples_per_voxel; /* S in [1, SALF_MAX_SAMPLES]; the workloads use 4, the paper 1        */
+  float t_min;               /* a ray stops after the voxel that leaves T < t_min; 0 = never stop */
+  float background[3];       /* added as T_end * background to the colour                           */
+  int32_t reserved;          /* must be 0                                                            */
+} salf_render_opts;
+
+/* Per-ray outputs, device FP32 unless noted; a NULL pointer means "not wanted".
+ *   rgb [n, 3]    C = sum w rgb + T_end * background   (Eq. 3)
+ *   depth [n]     D = sum w t_k, expected range along the ray in metres (not divided by O)
+ *   opacity [n]   O = 1 - T_end (the LiDAR ray-drop signal)
+ *   intensity [n] I = sum w i (LiDAR intensity channel; needs a scene with intensity)
+ *   t_end [n]     final transmittance T_end
+ *   n_hits [n]    int32, voxels composited (the voxel that crossed t_min included)
+ * Colour needs a scene with colour.  Compositing runs in FP32 with FP32 transmittance. */
+typedef struct {
+  float* rgb;
+  float* depth;
+  float* opacity;
+  float* intensity;
+  float* t_end;
+  int32_t* n_hits;
+} salf_outputs;
+
+/* Render one sensor (sensor != NULL, rays == NULL; ray generation is fused into the render
+ * kernel) or a batch of explicit rays (sensor == NULL, rays != NULL).  Output arrays have one
+ * row per ray in the ray-index order above.  Errors: INVALID_ARG, NOT_FOUND, DEVICE. */
+salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                        const salf_rays* rays, const salf_render_opts* opts, const salf_outputs* out,
+                        void* stream);
+
+/* The voxels each explicit ray hits, front to back, with no early termination:
+ *   d_counts int32 [n]: total hits of the ray (may exceed max_hits)
+ *   d_ids int32 [n, max_hits]: voxel ids (upload index); d_t_in, d_t_out float [n, max_hits]
+ * Entries past a ray's count are left untouched.  Errors: INVALID_ARG, NOT_FOUND, DEVICE. */
+salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
+                            int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream);
+
+/* ------------------------------------------------------------------ differentiation (Eq. 7) */
+
+/* Upstream gradients dL/d(output), device FP32, NULL = zero. */
+typedef struct {
+  const float* d_rgb;       /* [n, 3] */
+  const float* d_depth;     /* [n]    */
+  const float* d_opacity;   /* [n]    */
+  const float* d_intensity; /* [n]    */
+} salf_grads_in;
+
+/* Gradient of a corner-field render w.r.t. the raw corner logits, accumulated (+=) into
+ * d_dgeo [N, 8], d_drgb [N, 3, 8] and d_dint [N, 8] (NULL = not wanted; the caller zero-fills).
+ * `sensor`/`rays`, `opts` and the scene parameters must be those of the forward call, and
+ * `saved` must hold its t_end and n_hits (rgb/depth/intensity as well when their gradient is
+ * requested).  The kernel re-traverses each ray and recomputes transmittance front to back; no
+ * per-sample state is stored.  Accumulation uses FP32 atomics, so the summation order (and the
+ * last bits) vary between runs.  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field),
+ * DEVICE. */
+salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                                 const salf_rays* rays, const salf_render_opts* opts,
+                                 const salf_outputs* saved, const salf_grads_in* grads, float* d_dgeo,
+                                 float* d_drgb, float* d_dint, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SALF_H */

@@ -1,0 +1,309 @@
+"""Python binding of the renderer: torch tensors supply device memory, torch streams supply the
+HIP stream, and every call goes through the C ABI of libsalf.so (see include/salf.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Dict, Iterable, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call
+
+OUTPUT_NAMES = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+FIELDS = {"corner": _lib.FIELD_CORNER, "paper": _lib.FIELD_PAPER}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_dev(t: torch.Tensor, dtype, device, name, shape=None):
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Context:
+    """A libsalf context bound to one HIP device (one per device per process)."""
+    _cache: Dict[int, "Context"] = {}
+
+    def __init__(self, device_index: int):
+        h = C.c_void_p()
+        call("salf_create", int(device_index), C.byref(h))
+        self.handle = h
+        self.device = torch.device("cuda", device_index)
+
+    @classmethod
+    def get(cls, device=None) -> "Context":
+        idx = torch.device(device if device is not None else "cuda").index
+        idx = torch.cuda.current_device() if idx is None else idx
+        if idx not in cls._cache:
+            cls._cache[idx] = Context(idx)
+        return cls._cache[idx]
+
+    def sync(self):
+        call("salf_sync", self.handle, _stream(self.device))
+
+
+def sensor_struct(s: dict) -> _lib.Sensor:
+    """salf_sensor from a sensor description dict (keys as in the C struct)."""
+    st = _lib.Sensor()
+    for k in ("model", "width", "height"):
+        setattr(st, k, int(s[k]))
+    for k in ("fx", "fy", "cx", "cy", "max_theta", "elev_min", "elev_max", "az0", "t0", "dt_line", "t_near"):
+        setattr(st, k, float(s.get(k, 0.0)))
+    st.t_far = float(s.get("t_far", math.inf))
+    for k, n in (("R0", 9), ("p0", 3), ("v", 3), ("w", 3)):
+        vals = np.asarray(s.get(k, np.eye(3).ravel() if k == "R0" else np.zeros(n)), np.float64).reshape(n)
+        getattr(st, k)[:] = [float(x) for x in vals]
+    return st
+
+
+class Scene:
+    """A scene registered with libsalf.  Holds the device tensors it borrows (parameters and the
+    acceleration-structure workspace) for its lifetime."""
+
+    def __init__(self, voxels: torch.Tensor, geo: torch.Tensor, rgb: Optional[torch.Tensor],
+                 intensity: Optional[torch.Tensor], origin, root_size: float, root_dims, max_level: int,
+                 field: str = "corner"):
+        dev = geo.device
+        self.ctx = Context.get(dev)
+        n = int(voxels.shape[0])
+        _check_dev(voxels, torch.int32, dev, "voxels", (n, 4))
+        _check_dev(geo, torch.float32, dev, "geo", (n, 8))
+        if rgb is not None:
+            _check_dev(rgb, torch.float32, dev, "rgb", (n, 3, 8))
+        if intensity is not None:
+            _check_dev(intensity, torch.float32, dev, "intensity", (n, 8))
+        d = _lib.SceneDesc()
+        d.origin[:] = [float(x) for x in origin]
+        d.root_size = float(root_size)
+        d.root_dims[:] = [int(x) for x in root_dims]
+        d.max_level = int(max_level)
+        d.field = FIELDS[field]
+        d.reserved = 0
+        nbytes = C.c_size_t()
+        call("salf_scene_workspace_size", C.byref(d), n, C.byref(nbytes))
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+        sid = C.c_int32()
+
+        def chan(t):  # an empty tensor has no storage; any non-NULL pointer declares the channel
+            if t is None:
+                return None
+            return _ptr(t) if t.numel() else _ptr(self.workspace)
+
+        call("salf_scene_create", self.ctx.handle, C.byref(d), n, _ptr(voxels), _ptr(geo), chan(rgb), chan(intensity),
+             _ptr(self.workspace), int(self.workspace.numel()), _stream(dev), C.byref(sid))
+        self.id = int(sid.value)
+        self.desc = d
+        self.device = dev
+        self.n = n
+        self.field = field
+        self.geo, self.rgb, self.intensity = geo, rgb, intensity
+        self._voxels = voxels
+
+    @classmethod
+    def from_data(cls, data, device="cuda", field: str = "corner", rgb: bool = True, intensity: bool = True,
+                  requires_grad: bool = False) -> "Scene":
+        """Upload a scene given as numpy arrays (attributes origin, root_size, root_dims, max_level,
+        voxels [N,4] int32, z_geo [N,8], z_rgb [N,3,8], z_int [N,8] or None)."""
+        dev = torch.device(device)
+
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt).contiguous()
+
+        vox = up(data.voxels, torch.int32)
+        geo = up(data.z_geo, torch.float32)
+        col = up(data.z_rgb, torch.float32) if (rgb and data.z_rgb is not None) else None
+        ity = up(data.z_int, torch.float32) if (intensity and data.z_int is not None) else None
+        if requires_grad:
+            for t in (geo, col, ity):
+                if t is not None:
+                    t.requires_grad_(True)
+        return cls(vox, geo, col, ity, data.origin, data.root_size, data.root_dims, data.max_level, field)
+
+    def stats(self) -> dict:
+        s = _lib.SceneStats()
+        call("salf_scene_get_stats", self.ctx.handle, self.id, C.byref(s))
+        return {k: int(getattr(s, k)) for k, _ in _lib.SceneStats._fields_}
+
+    def destroy(self):
+        if self.id >= 0:
+            call("salf_scene_destroy", self.ctx.handle, self.id)
+            self.id = -1
+
+    def __del__(self):
+        try:
+            if getattr(self, "id", -1) >= 0 and _lib._lib is not None:
+                _lib.lib().salf_scene_destroy(self.ctx.handle, self.id)
+        except Exception:
+            pass
+
+
+def ray_count(sensor: dict) -> int:
+    n = C.c_int64()
+    call("salf_sensor_ray_count", C.byref(sensor_struct(sensor)), C.byref(n))
+    return int(n.value)
+
+
+def generate_rays(sensor: dict, device="cuda") -> Dict[str, torch.Tensor]:
+    """Materialize a sensor's rays on the GPU: o [n,3], d [n,3], t [n] (float32), valid [n] (uint8)."""
+    dev = torch.device(device)
+    ctx = Context.get(dev)
+    n = ray_count(sensor)
+    o = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    d = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    v = torch.empty(n, dtype=torch.uint8, device=dev)
+    call("salf_generate_rays", ctx.handle, C.byref(sensor_struct(sensor)), _ptr(o), _ptr(d), _ptr(t), _ptr(v),
+         _stream(dev))
+    return {"o": o, "d": d, "t": t, "valid": v}
+
+
+def _opts(samples, t_min, background) -> _lib.RenderOpts:
+    op = _lib.RenderOpts()
+    op.samples_per_voxel = int(samples)
+    op.t_min = float(t_min)
+    op.background[:] = [float(x) for x in background]
+    op.reserved = 0
+    return op
+
+
+def _rays_struct(o, d, t_near, t_far, device, image_width=0):
+    _check_dev(o, torch.float32, device, "o")
+    _check_dev(d, torch.float32, device, "d")
+    if o.shape != d.shape or o.dim() != 2 or o.shape[1] != 3:
+        raise ValueError("o and d must both be [n, 3]")
+    r = _lib.Rays()
+    r.o = o.data_ptr()
+    r.d = d.data_ptr()
+    r.n = int(o.shape[0])
+    r.t_near = float(t_near)
+    r.t_far = float(t_far)
+    r.image_width = int(image_width)
+    r.reserved = 0
+    return r
+
+
+def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor] = None,
+           d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
+           outputs: Iterable[str] = ("rgb", "depth", "opacity"), t_near: float = 0.0, t_far: float = math.inf,
+           out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0) -> Dict[str, torch.Tensor]:
+    """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
+    image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
+    Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
+    n_hits int32 [n])."""
+    dev = scene.device
+    outputs = tuple(outputs)
+    for k in outputs:
+        if k not in OUTPUT_NAMES:
+            raise ValueError(f"unknown output {k}")
+    sen = rays = None
+    if sensor is not None:
+        sen = sensor_struct(sensor)
+        n = ray_count(sensor)
+    else:
+        rays = _rays_struct(o, d, t_near, t_far, dev, image_width)
+        n = int(rays.n)
+    res = {} if out is None else dict(out)
+    for k in outputs:
+        if k not in res:
+            shape = (n, 3) if k == "rgb" else (n,)
+            res[k] = torch.empty(shape, dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev)
+    ob = _lib.Outputs()
+    for k in OUTPUT_NAMES:
+        setattr(ob, k, res[k].data_ptr() if k in res else None)
+    call("salf_render", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(ob),
+         _stream(dev))
+    return res
+
+
+def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_near: float = 0.0,
+               t_far: float = math.inf):
+    """Voxels hit by each ray, front to back: counts [n] and ids/t_in/t_out [n, max_hits]
+    (entries past a ray's count are -1 / NaN)."""
+    dev = scene.device
+    rays = _rays_struct(o, d, t_near, t_far, dev)
+    n = int(rays.n)
+    counts = torch.empty(n, dtype=torch.int32, device=dev)
+    ids = torch.full((n, max_hits), -1, dtype=torch.int32, device=dev)
+    ti = torch.full((n, max_hits), float("nan"), dtype=torch.float32, device=dev)
+    to = torch.full((n, max_hits), float("nan"), dtype=torch.float32, device=dev)
+    call("salf_trace_hits", scene.ctx.handle, scene.id, C.byref(rays), int(max_hits), _ptr(counts), _ptr(ids),
+         _ptr(ti), _ptr(to), _stream(dev))
+    return counts, ids, ti, to
+
+
+def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[str, Optional[torch.Tensor]],
+                    sensor: Optional[dict] = None, o=None, d=None, samples: int = 4, t_min: float = 1e-6,
+                    background=(0.0, 0.0, 0.0), t_near: float = 0.0, t_far: float = math.inf,
+                    d_geo=None, d_rgb=None, d_int=None, image_width: int = 0):
+    """Accumulate dL/d(params) of a corner-field render into d_geo/d_rgb/d_int (allocated zeroed if
+    None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
+    dev = scene.device
+    if d_geo is None:
+        d_geo = torch.zeros_like(scene.geo, memory_format=torch.contiguous_format)
+    if d_rgb is None and scene.rgb is not None and grads.get("rgb") is not None:
+        d_rgb = torch.zeros_like(scene.rgb, memory_format=torch.contiguous_format)
+    if d_int is None and scene.intensity is not None and grads.get("intensity") is not None:
+        d_int = torch.zeros_like(scene.intensity, memory_format=torch.contiguous_format)
+    sen = rays = None
+    if sensor is not None:
+        sen = sensor_struct(sensor)
+    else:
+        rays = _rays_struct(o, d, t_near, t_far, dev, image_width)
+    sv = _lib.Outputs()
+    for k in OUTPUT_NAMES:
+        t = saved.get(k)
+        setattr(sv, k, t.data_ptr() if t is not None else None)
+    g = _lib.GradsIn()
+    for k, f in (("rgb", "d_rgb"), ("depth", "d_depth"), ("opacity", "d_opacity"), ("intensity", "d_intensity")):
+        t = grads.get(k)
+        if t is not None:
+            t = t.contiguous()
+            grads[k] = t
+        setattr(g, f, t.data_ptr() if t is not None else None)
+    call("salf_render_backward", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(sv),
+         C.byref(g), _ptr(d_geo), _ptr(d_rgb), _ptr(d_int), _stream(dev))
+    return d_geo, d_rgb, d_int
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable corner-field render.  apply(geo, rgb, intensity, scene, sensor, o, d, opts) ->
+    (rgb, depth, opacity, intensity); geo/rgb/intensity must be the scene's own parameter
+    tensors (the render reads them in place).  rgb/intensity outputs are empty tensors when the
+    scene lacks that parameter."""
+
+    @staticmethod
+    def forward(ctx, geo, rgb, intensity, scene: Scene, sensor, o, d, opts: dict):
+        want = ["depth", "opacity", "t_end", "n_hits"]
+        if rgb is not None:
+            want.append("rgb")
+        if intensity is not None:
+            want.append("intensity")
+        res = render(scene, sensor=sensor, o=o, d=d, outputs=want, **opts)
+        ctx.scene, ctx.sensor, ctx.o, ctx.d, ctx.opts = scene, sensor, o, d, opts
+        ctx.saved = res
+        empty = torch.empty(0, device=geo.device)
+        ctx.mark_non_differentiable(res["t_end"], res["n_hits"])
+        return res.get("rgb", empty), res["depth"], res["opacity"], res.get("intensity", empty)
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_opacity, g_int):
+        sc = ctx.scene
+        grads = {"rgb": g_rgb if sc.rgb is not None and g_rgb is not None and g_rgb.numel() else None,
+                 "depth": g_depth, "opacity": g_opacity,
+                 "intensity": g_int if sc.intensity is not None and g_int is not None and g_int.numel() else None}
+        dg, dr, di = render_backward(sc, ctx.saved, grads, sensor=ctx.sensor, o=ctx.o, d=ctx.d, **ctx.opts)
+        return dg, dr, di, None, None, None, None, None

@@ -1,0 +1,382 @@
+// C ABI entry points: argument validation, the scene registry and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace salf {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+salf_status set_error(salf_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+salf_status check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SALF_OK;
+  return set_error(SALF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Scene {
+  bool live = false;
+  salf_scene_desc desc;
+  int64_t n = 0;
+  SceneLayout layout;
+  SceneView view;
+  BuildCounters counters;
+};
+
+}  // namespace salf
+
+struct salf_context {
+  int device = 0;
+  std::mutex mu;
+  std::vector<salf::Scene> scenes;
+};
+
+using namespace salf;
+
+namespace {
+
+// RAII guard selecting the context's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+salf_status validate_desc(const salf_scene_desc* d) {
+  if (!d) return set_error(SALF_ERR_INVALID_ARG, "scene desc is NULL");
+  if (!(d->root_size > 0.0) || !isfinite(d->root_size))
+    return set_error(SALF_ERR_INVALID_ARG, "root_size must be finite and > 0");
+  if (d->max_level < 0 || d->max_level > SALF_MAX_LEVEL)
+    return set_error(SALF_ERR_INVALID_ARG, "max_level %d outside [0, %d]", d->max_level, SALF_MAX_LEVEL);
+  for (int a = 0; a < 3; ++a) {
+    if (!isfinite(d->origin[a])) return set_error(SALF_ERR_INVALID_ARG, "origin[%d] is not finite", a);
+    if (d->root_dims[a] < 1) return set_error(SALF_ERR_INVALID_ARG, "root_dims[%d] must be >= 1", a);
+    if (((int64_t)d->root_dims[a] << d->max_level) >= SALF_MAX_FINE_CELLS)
+      return set_error(SALF_ERR_INVALID_ARG, "root_dims[%d] << max_level must be < %d", a, SALF_MAX_FINE_CELLS);
+  }
+  if (d->field != SALF_FIELD_CORNER && d->field != SALF_FIELD_PAPER)
+    return set_error(SALF_ERR_INVALID_ARG, "unknown field mode %d", d->field);
+  if (d->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
+  return SALF_OK;
+}
+
+salf_status validate_sensor(const salf_sensor* s) {
+  if (!s) return set_error(SALF_ERR_INVALID_ARG, "sensor is NULL");
+  if (s->model != SALF_PINHOLE && s->model != SALF_FISHEYE_EQUIDISTANT && s->model != SALF_LIDAR_SPINNING)
+    return set_error(SALF_ERR_INVALID_ARG, "unknown sensor model %d", s->model);
+  if (s->width < 1 || s->height < 1) return set_error(SALF_ERR_INVALID_ARG, "sensor width and height must be >= 1");
+  if ((int64_t)s->width * s->height > ((int64_t)1 << 31))
+    return set_error(SALF_ERR_INVALID_ARG, "sensor has more than 2^31 rays");
+  if (s->model != SALF_LIDAR_SPINNING) {
+    if (!(s->fx != 0.0f) || !isfinite(s->fx)) return set_error(SALF_ERR_INVALID_ARG, "fx must be finite and nonzero");
+    if (s->model == SALF_PINHOLE && (!(s->fy != 0.0f) || !isfinite(s->fy)))
+      return set_error(SALF_ERR_INVALID_ARG, "fy must be finite and nonzero");
+  }
+  if (!(s->t_near >= 0.0f) || !(s->t_near < s->t_far))
+    return set_error(SALF_ERR_INVALID_ARG, "need 0 <= t_near < t_far");
+  return SALF_OK;
+}
+
+salf_status validate_rays(const salf_rays* r) {
+  if (!r) return set_error(SALF_ERR_INVALID_ARG, "rays is NULL");
+  if (r->n < 0 || r->n > ((int64_t)1 << 31)) return set_error(SALF_ERR_INVALID_ARG, "ray count out of range");
+  if (r->n > 0 && (!r->o || !r->d)) return set_error(SALF_ERR_INVALID_ARG, "ray origin/direction pointer is NULL");
+  if (!(r->t_near >= 0.0f) || !(r->t_near < r->t_far))
+    return set_error(SALF_ERR_INVALID_ARG, "need 0 <= t_near < t_far");
+  if (r->image_width < 0 || r->reserved != 0)
+    return set_error(SALF_ERR_INVALID_ARG, "image_width must be >= 0 and reserved 0");
+  return SALF_OK;
+}
+
+salf_status validate_opts(const salf_render_opts* o) {
+  if (!o) return set_error(SALF_ERR_INVALID_ARG, "render opts is NULL");
+  if (o->samples_per_voxel < 1 || o->samples_per_voxel > SALF_MAX_SAMPLES)
+    return set_error(SALF_ERR_INVALID_ARG, "samples_per_voxel %d outside [1, %d]", o->samples_per_voxel,
+                     SALF_MAX_SAMPLES);
+  if (!(o->t_min >= 0.0f) || !(o->t_min <= 1.0f)) return set_error(SALF_ERR_INVALID_ARG, "t_min must be in [0, 1]");
+  if (o->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
+  return SALF_OK;
+}
+
+salf_status find_scene(salf_context* ctx, int32_t id, Scene** out) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  if (id < 0 || id >= (int32_t)ctx->scenes.size() || !ctx->scenes[id].live)
+    return set_error(SALF_ERR_NOT_FOUND, "no scene with id %d", id);
+  *out = &ctx->scenes[id];
+  return SALF_OK;
+}
+
+// Fill the parts of RenderParams shared by render and backward.
+salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
+                           const salf_render_opts* opts, RenderParams* p, int* field) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  if ((sensor == nullptr) == (rays == nullptr))
+    return set_error(SALF_ERR_INVALID_ARG, "pass exactly one of sensor and rays");
+  if ((st = validate_opts(opts))) return st;
+  memset(p, 0, sizeof(*p));
+  p->scene = sc->view;
+  if (sensor) {
+    if ((st = validate_sensor(sensor))) return st;
+    p->sensor = *sensor;
+    p->use_sensor = 1;
+    p->tiled = 1;
+    p->img_w = sensor->width;
+    p->img_h = sensor->height;
+    p->n = (int64_t)sensor->width * sensor->height;
+  } else {
+    if ((st = validate_rays(rays))) return st;
+    p->ro = rays->o;
+    p->rd = rays->d;
+    p->n = rays->n;
+    p->t_near = rays->t_near;
+    p->t_far = rays->t_far;
+    if (rays->image_width > 0) {
+      p->tiled = 1;
+      p->img_w = rays->image_width;
+      p->img_h = (int32_t)((rays->n + rays->image_width - 1) / rays->image_width);
+    }
+    if (p->n > 0 && ((((uintptr_t)rays->o) & 3u) || (((uintptr_t)rays->d) & 3u)))
+      return set_error(SALF_ERR_INVALID_ARG, "ray buffers must be 4-byte aligned");
+  }
+  p->tiles_x = (p->img_w + 7) / 8;
+  p->tiles_y = (p->img_h + 7) / 8;
+  p->S = opts->samples_per_voxel;
+  p->t_min = opts->t_min;
+  for (int c = 0; c < 3; ++c) p->bg[c] = opts->background[c];
+  *field = sc->desc.field;
+  return SALF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t salf_abi_version(void) { return SALF_ABI_VERSION; }
+
+const char* salf_last_error(void) { return g_err; }
+
+salf_status salf_create(int32_t hip_device, salf_context** out) {
+  if (!out) return set_error(SALF_ERR_INVALID_ARG, "out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+    return set_error(SALF_ERR_INVALID_ARG, "no HIP device %d (found %d)", hip_device, count);
+  salf_context* c = new (std::nothrow) salf_context();
+  if (!c) return set_error(SALF_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->device = hip_device;
+  *out = c;
+  return SALF_OK;
+}
+
+salf_status salf_destroy(salf_context* ctx) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  delete ctx;
+  return SALF_OK;
+}
+
+salf_status salf_sync(salf_context* ctx, void* stream) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  DeviceGuard g(ctx->device);
+  salf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  if (st) return st;
+  return check_hip(hipGetLastError(), "kernel execution");
+}
+
+salf_status salf_scene_workspace_size(const salf_scene_desc* desc, int64_t n_voxels, size_t* bytes) {
+  salf_status st = validate_desc(desc);
+  if (st) return st;
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_voxels < 0 || n_voxels > ((int64_t)1 << 30)) return set_error(SALF_ERR_INVALID_ARG, "n_voxels out of range");
+  SceneLayout L;
+  scene_layout(*desc, n_voxels, &L);
+  *bytes = L.total;
+  return SALF_OK;
+}
+
+salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, int64_t n_voxels,
+                              const int32_t* d_voxels, const float* d_geo, const float* d_rgb, const float* d_int,
+                              void* d_workspace, size_t ws_bytes, void* stream, int32_t* scene_id) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  salf_status st = validate_desc(desc);
+  if (st) return st;
+  if (!scene_id) return set_error(SALF_ERR_INVALID_ARG, "scene_id is NULL");
+  if (n_voxels < 0 || n_voxels > ((int64_t)1 << 30)) return set_error(SALF_ERR_INVALID_ARG, "n_voxels out of range");
+  if (n_voxels > 0 && (!d_voxels || !d_geo)) return set_error(SALF_ERR_INVALID_ARG, "voxels and geo are required");
+  if (!d_workspace) return set_error(SALF_ERR_INVALID_ARG, "workspace is NULL");
+  const void* ptrs[5] = {d_voxels, d_geo, d_rgb, d_int, d_workspace};
+  for (const void* q : ptrs)
+    if (q && !aligned16(q)) return set_error(SALF_ERR_INVALID_ARG, "device buffers must be 16-byte aligned");
+  SceneLayout L;
+  scene_layout(*desc, n_voxels, &L);
+  if (ws_bytes < L.total)
+    return set_error(SALF_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, the scene needs %zu", ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = check_hip(launch_scene_build(*desc, n_voxels, d_voxels, L, d_workspace, s), "scene build launch")))
+    return st;
+  BuildCounters c;
+  if ((st = check_hip(hipMemcpyAsync(&c, (char*)d_workspace + L.counters_off, sizeof(c), hipMemcpyDeviceToHost, s),
+                      "copy build counters")))
+    return st;
+  if ((st = check_hip(hipStreamSynchronize(s), "scene build"))) return st;
+  if (c.error_bits & 1)
+    return set_error(SALF_ERR_INVALID_ARG, "voxel %d has a level outside [0, %d] or coordinates outside the grid",
+                     c.first_bad, desc->max_level);
+  if (c.error_bits & 2)
+    return set_error(SALF_ERR_INVALID_ARG, "voxel %d overlaps or repeats another voxel", c.first_bad);
+  if (c.error_bits & 4) return set_error(SALF_ERR_OUT_OF_MEMORY, "node table overflow during the scene build");
+
+  Scene sc;
+  sc.live = true;
+  sc.desc = *desc;
+  sc.n = n_voxels;
+  sc.layout = L;
+  sc.counters = c;
+  SceneView& v = sc.view;
+  v.root = (const int32_t*)((char*)d_workspace + L.root_off);
+  v.nodes = (const int32_t*)((char*)d_workspace + L.nodes_off);
+  v.geo = d_geo;
+  v.rgb = d_rgb;
+  v.inten = d_int;
+  for (int a = 0; a < 3; ++a) {
+    v.dims[a] = desc->root_dims[a];
+    v.org[a] = desc->origin[a];
+    v.org32[a] = (float)desc->origin[a];
+  }
+  v.K = desc->max_level;
+  v.gs = (double)(1 << desc->max_level) / desc->root_size;
+  v.gs32 = (float)v.gs;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (size_t i = 0; i < ctx->scenes.size(); ++i) {
+    if (!ctx->scenes[i].live) {
+      ctx->scenes[i] = sc;
+      *scene_id = (int32_t)i;
+      return SALF_OK;
+    }
+  }
+  ctx->scenes.push_back(sc);
+  *scene_id = (int32_t)(ctx->scenes.size() - 1);
+  return SALF_OK;
+}
+
+salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  if (!out) return set_error(SALF_ERR_INVALID_ARG, "out is NULL");
+  out->n_voxels = sc->n;
+  out->n_nodes = sc->counters.n_nodes;
+  out->n_root_cells = sc->layout.n_root;
+  out->n_occupied_roots = sc->counters.n_occupied;
+  out->workspace_bytes = sc->layout.total;
+  return SALF_OK;
+}
+
+salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  sc->live = false;
+  return SALF_OK;
+}
+
+salf_status salf_sensor_ray_count(const salf_sensor* sensor, int64_t* n_rays) {
+  salf_status st = validate_sensor(sensor);
+  if (st) return st;
+  if (!n_rays) return set_error(SALF_ERR_INVALID_ARG, "n_rays is NULL");
+  *n_rays = (int64_t)sensor->width * sensor->height;
+  return SALF_OK;
+}
+
+salf_status salf_generate_rays(salf_context* ctx, const salf_sensor* sensor, float* d_o, float* d_d, float* d_t,
+                               uint8_t* d_valid, void* stream) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  salf_status st = validate_sensor(sensor);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_raygen(*sensor, d_o, d_d, d_t, d_valid, (hipStream_t)stream), "ray generation launch");
+}
+
+salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
+                        const salf_render_opts* opts, const salf_outputs* out, void* stream) {
+  RenderParams p;
+  int field = 0;
+  salf_status st = prepare_render(ctx, scene_id, sensor, rays, opts, &p, &field);
+  if (st) return st;
+  if (!out) return set_error(SALF_ERR_INVALID_ARG, "outputs is NULL");
+  if (out->rgb && !p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
+  if (out->intensity && !p.scene.inten)
+    return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
+  p.out = *out;
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_render(p, field, (hipStream_t)stream), "render launch");
+}
+
+salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
+                            int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  if ((st = validate_rays(rays))) return st;
+  if (max_hits < 0) return set_error(SALF_ERR_INVALID_ARG, "max_hits must be >= 0");
+  if (rays->n > 0 && (!d_counts || (max_hits > 0 && (!d_ids || !d_t_in || !d_t_out))))
+    return set_error(SALF_ERR_INVALID_ARG, "output pointer is NULL");
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_trace(sc->view, *rays, max_hits, d_counts, d_ids, d_t_in, d_t_out, (hipStream_t)stream),
+                   "trace launch");
+}
+
+salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
+                                 const salf_render_opts* opts, const salf_outputs* saved, const salf_grads_in* grads,
+                                 float* d_dgeo, float* d_drgb, float* d_dint, void* stream) {
+  BackwardParams b;
+  int field = 0;
+  salf_status st = prepare_render(ctx, scene_id, sensor, rays, opts, &b.fwd, &field);
+  if (st) return st;
+  if (field != SALF_FIELD_CORNER)
+    return set_error(SALF_ERR_UNSUPPORTED, "the backward pass covers the corner-interpolated field");
+  if (!saved || !grads) return set_error(SALF_ERR_INVALID_ARG, "saved outputs and gradients are required");
+  if (!saved->t_end || !saved->n_hits) return set_error(SALF_ERR_INVALID_ARG, "saved t_end and n_hits are required");
+  if (grads->d_rgb && (!saved->rgb || !b.fwd.scene.rgb))
+    return set_error(SALF_ERR_INVALID_ARG, "colour gradient needs the saved colour and a scene with colour");
+  if (grads->d_depth && !saved->depth) return set_error(SALF_ERR_INVALID_ARG, "depth gradient needs the saved depth");
+  if (grads->d_intensity && (!saved->intensity || !b.fwd.scene.inten))
+    return set_error(SALF_ERR_INVALID_ARG, "intensity gradient needs the saved intensity and a scene with intensity");
+  if (d_drgb && !b.fwd.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "scene has no colour parameters");
+  if (d_dint && !b.fwd.scene.inten) return set_error(SALF_ERR_INVALID_ARG, "scene has no intensity parameters");
+  b.fwd.out = *saved;
+  b.g = *grads;
+  b.dgeo = d_dgeo;
+  b.drgb = d_drgb;
+  b.dint = d_dint;
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_backward(b, (hipStream_t)stream), "backward launch");
+}
+
+}  // extern "C"

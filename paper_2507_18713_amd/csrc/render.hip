@@ -1,0 +1,437 @@
+// Forward rendering: per ray, front-to-back traversal of the occupied voxels it hits, S midpoint
+// samples of each voxel's local field per segment, and alpha compositing of colour, depth,
+// intensity and opacity with FP32 transmittance and early termination (Eq. 1-4, Sec. 3.2).
+//
+// Work mapping: one lane per ray.  In sensor mode a wave64 covers an 8x8 tile of pixels (or of
+// LiDAR beams x columns) so that the lanes of a wave walk nearby voxels and share their parameter
+// cache lines; ray generation is fused (no ray buffer in HBM).
+#include "internal.hpp"
+
+namespace salf {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Composited state of one ray.
+struct Accum {
+  float T, C[3], D, I;
+  int32_t n;
+};
+
+// Shade one voxel segment [ti, to] and composite it into acc.  Returns false once the ray has
+// become opaque enough to stop (T < t_min after the voxel).
+template <int FIELD, bool RGB, bool INT>
+__device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], int32_t v,
+                                            const int32_t lo[3], int32_t size, float ti, float to, int S, float t_min,
+                                            Accum& acc) {
+  // corner parameters of the voxel (coalescing across lanes comes from coherent rays)
+  float g[8], c[3][8], it[8];
+  {
+    const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
+    const float4 g0 = gp[0], g1 = gp[1];
+    g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w; g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
+  }
+  if (RGB) {
+    const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float4 a = cp[2 * ch], b = cp[2 * ch + 1];
+      c[ch][0] = a.x; c[ch][1] = a.y; c[ch][2] = a.z; c[ch][3] = a.w;
+      c[ch][4] = b.x; c[ch][5] = b.y; c[ch][6] = b.z; c[ch][7] = b.w;
+    }
+  }
+  if (INT) {
+    const float4* ip = reinterpret_cast<const float4*>(s.inten + (int64_t)v * 8);
+    const float4 a = ip[0], b = ip[1];
+    it[0] = a.x; it[1] = a.y; it[2] = a.z; it[3] = a.w; it[4] = b.x; it[5] = b.y; it[6] = b.z; it[7] = b.w;
+  }
+  float shc[3] = {0.0f, 0.0f, 0.0f};  // view-dependent colour term (paper field)
+  if (FIELD == SALF_FIELD_CORNER) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = softplus_f(g[i]);
+    if (RGB) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[ch][i] = sigmoid_f(c[ch][i]);
+    }
+    if (INT) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) it[i] = sigmoid_f(it[i]);
+    }
+  } else if (RGB) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) shc[ch] = c[ch][3] * sh[0] + c[ch][4] * sh[1] + c[ch][5] * sh[2] + c[ch][6] * sh[3];
+  }
+
+  // sample positions relative to the voxel, formed in FP64 and kept small in FP32
+  const double dt = (double)to - (double)ti;
+  const float delta = (float)(dt / S);  // length of one piece
+  float rel[3], stp[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    rel[a] = (float)((f.ogd[a] - (double)lo[a]) + (double)ti * f.dgd[a]);
+    stp[a] = (float)(dt * f.dgd[a] / S);
+  }
+  const float sc = 2.0f / (float)size;
+
+  for (int k = 0; k < S; ++k) {
+    const float fk = (float)k + 0.5f;
+    float x[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = fminf(fmaxf((rel[a] + fk * stp[a]) * sc - 1.0f, -1.0f), 1.0f);
+    float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
+    if (FIELD == SALF_FIELD_CORNER) {
+      float w[8];
+      corner_weights(x, w);
+      sigma = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sigma += w[i] * g[i];
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          float a = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) a += w[i] * c[ch][i];
+          col[ch] = a;
+        }
+      }
+      if (INT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) inten += w[i] * it[i];
+      }
+    } else {
+      sigma = __expf(g[0] * x[0] + g[1] * x[1] + g[2] * x[2] + g[3]);
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = sigmoid_f(c[ch][0] * x[0] + c[ch][1] * x[1] + c[ch][2] * x[2] + shc[ch]);
+      }
+      if (INT) inten = sigmoid_f(it[0] * x[0] + it[1] * x[1] + it[2] * x[2] + it[3]);
+    }
+    const float e = __expf(-sigma * delta);
+    const float wgt = acc.T * (1.0f - e);
+    if (RGB) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc.C[ch] += wgt * col[ch];
+    }
+    acc.D += wgt * (ti + fk * delta);
+    if (INT) acc.I += wgt * inten;
+    acc.T *= e;
+  }
+  acc.n += 1;
+  return !(acc.T < t_min);
+}
+
+// The ray of this lane: its index and grid frame.  Returns false for lanes without a ray.
+__device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t& ray, float d[3], RayFrame& f) {
+  const int lane = threadIdx.x & 63;
+  int col = 0, row = 0;
+  if (p.tiled) {
+    const int64_t wave = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+    const int tx = (int)(wave % p.tiles_x), ty = (int)(wave / p.tiles_x);
+    col = tx * 8 + (lane & 7);
+    row = ty * 8 + (lane >> 3);
+    if (ty >= p.tiles_y || col >= p.img_w || row >= p.img_h) return false;
+    ray = (int64_t)row * p.img_w + col;
+    if (ray >= p.n) return false;
+  } else {
+    ray = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (ray >= p.n) return false;
+  }
+  float o[3];
+  bool valid = true;
+  float tn = p.t_near, tf = p.t_far;
+  if (p.use_sensor) {
+    float tt;
+    valid = sensor_ray(p.sensor, col, row, o, d, tt);
+    tn = p.sensor.t_near;
+    tf = p.sensor.t_far;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      o[a] = p.ro[ray * 3 + a];
+      d[a] = p.rd[ray * 3 + a];
+    }
+  }
+  f = make_frame(p.scene, o, d, tn, tf);
+  if (!valid) f.valid = false;
+  return true;
+}
+
+template <int FIELD, bool RGB, bool INT>
+__global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
+  int64_t ray;
+  float d[3];
+  RayFrame f;
+  if (!lane_ray(p, ray, d, f)) return;
+  float sh[4] = {kShC0, kShC1 * d[0], kShC1 * d[1], kShC1 * d[2]};
+  Accum acc;
+  acc.T = 1.0f;
+  acc.C[0] = acc.C[1] = acc.C[2] = 0.0f;
+  acc.D = acc.I = 0.0f;
+  acc.n = 0;
+  const int S = p.S;
+  const float t_min = p.t_min;
+  traverse(p.scene, f, [&](int32_t v, const int32_t lo[3], int32_t size, float ti, float to) -> bool {
+    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, v, lo, size, ti, to, S, t_min, acc);
+  });
+  const salf_outputs& out = p.out;
+  if (out.rgb) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = acc.C[ch] + acc.T * p.bg[ch];
+  }
+  if (out.depth) out.depth[ray] = acc.D;
+  if (out.opacity) out.opacity[ray] = 1.0f - acc.T;
+  if (out.intensity) out.intensity[ray] = acc.I;
+  if (out.t_end) out.t_end[ray] = acc.T;
+  if (out.n_hits) out.n_hits[ray] = acc.n;
+}
+
+__global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays r, int32_t max_hits, int32_t* counts,
+                                                         int32_t* ids, float* t_in, float* t_out) {
+  const int64_t ray = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (ray >= r.n) return;
+  float o[3], d[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o[a] = r.o[ray * 3 + a];
+    d[a] = r.d[ray * 3 + a];
+  }
+  const RayFrame f = make_frame(s, o, d, r.t_near, r.t_far);
+  int32_t n = 0;
+  const int64_t base = ray * (int64_t)max_hits;
+  traverse(s, f, [&](int32_t v, const int32_t*, int32_t, float ti, float to) -> bool {
+    if (n < max_hits) {
+      ids[base + n] = v;
+      t_in[base + n] = ti;
+      t_out[base + n] = to;
+    }
+    ++n;
+    return true;
+  });
+  counts[ray] = n;
+}
+
+__global__ __launch_bounds__(kThreads) void raygen_kernel(salf_sensor s, float* o, float* d, float* t, uint8_t* valid) {
+  const int64_t ray = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t n = (int64_t)s.width * s.height;
+  if (ray >= n) return;
+  const int col = (int)(ray % s.width), row = (int)(ray / s.width);
+  float ro[3], rd[3], tt;
+  const bool ok = sensor_ray(s, col, row, ro, rd, tt);
+  if (o) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[ray * 3 + a] = ro[a];
+  }
+  if (d) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[ray * 3 + a] = rd[a];
+  }
+  if (t) t[ray] = tt;
+  if (valid) valid[ray] = ok ? 1 : 0;
+}
+
+// Backward of the corner-field render (the derivation is the one of the oracle's gradient):
+// with w_j = T_j - T_{j+1} and the suffix sums of a ray formed by prefix subtraction from the
+// saved outputs (sum_{k>j} w_k c_k + T_end bg = C - sum_{k<=j} w_k c_k, likewise for D and I),
+//   dL/dtau_j = gC.(T_{j+1} c_j - sufC_j) + gD (T_{j+1} t_j - sufD_j) + gI (T_{j+1} i_j - sufI_j)
+//               + gO T_end,
+// dsigma_j = dL/dtau_j * delta_j, dc_j = gC w_j, di_j = gI w_j; corner logits get these times
+// the trilinear weight and the activation's derivative (softplus' = sigmoid, sigmoid' = s(1-s)).
+// Transmittance is recomputed front to back; the ray stops after the saved number of voxels.
+template <bool RGB, bool INT>
+__global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
+  const RenderParams& p = b.fwd;
+  int64_t ray;
+  float dir[3];
+  RayFrame f;
+  if (!lane_ray(p, ray, dir, f)) return;
+  const int32_t n_stop = p.out.n_hits[ray];
+  if (n_stop <= 0) return;
+  const float T_end = p.out.t_end[ray];
+  float gC[3] = {0.0f, 0.0f, 0.0f}, Cs[3] = {0.0f, 0.0f, 0.0f};
+  if (RGB) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      gC[ch] = b.g.d_rgb[ray * 3 + ch];
+      Cs[ch] = p.out.rgb[ray * 3 + ch];
+    }
+  }
+  const float gD = b.g.d_depth ? b.g.d_depth[ray] : 0.0f;
+  const float Ds = b.g.d_depth ? p.out.depth[ray] : 0.0f;
+  const float gI = INT ? b.g.d_intensity[ray] : 0.0f;
+  const float Is = INT ? p.out.intensity[ray] : 0.0f;
+  const float gOT = (b.g.d_opacity ? b.g.d_opacity[ray] : 0.0f) * T_end;
+  const SceneView& s = p.scene;
+  const int S = p.S;
+  float T = 1.0f, PC[3] = {0.0f, 0.0f, 0.0f}, PD = 0.0f, PI = 0.0f;
+  int32_t count = 0;
+  traverse(s, f, [&](int32_t v, const int32_t lo[3], int32_t size, float ti, float to) -> bool {
+    float zg[8], sp[8], zr[3][8], cr[3][8], zi[8], ci[8];
+    {
+      const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
+      const float4 g0 = gp[0], g1 = gp[1];
+      zg[0] = g0.x; zg[1] = g0.y; zg[2] = g0.z; zg[3] = g0.w; zg[4] = g1.x; zg[5] = g1.y; zg[6] = g1.z; zg[7] = g1.w;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sp[i] = softplus_f(zg[i]);
+    if (RGB) {
+      const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float4 a = cp[2 * ch], q = cp[2 * ch + 1];
+        zr[ch][0] = a.x; zr[ch][1] = a.y; zr[ch][2] = a.z; zr[ch][3] = a.w;
+        zr[ch][4] = q.x; zr[ch][5] = q.y; zr[ch][6] = q.z; zr[ch][7] = q.w;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cr[ch][i] = sigmoid_f(zr[ch][i]);
+      }
+    }
+    if (INT) {
+      const float4* ip = reinterpret_cast<const float4*>(s.inten + (int64_t)v * 8);
+      const float4 a = ip[0], q = ip[1];
+      zi[0] = a.x; zi[1] = a.y; zi[2] = a.z; zi[3] = a.w; zi[4] = q.x; zi[5] = q.y; zi[6] = q.z; zi[7] = q.w;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ci[i] = sigmoid_f(zi[i]);
+    }
+    const double dt = (double)to - (double)ti;
+    const float delta = (float)(dt / S);
+    float rel[3], stp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rel[a] = (float)((f.ogd[a] - (double)lo[a]) + (double)ti * f.dgd[a]);
+      stp[a] = (float)(dt * f.dgd[a] / S);
+    }
+    const float sc = 2.0f / (float)size;
+    float ag[8], ar[3][8], ai[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ag[i] = 0.0f;
+      ai[i] = 0.0f;
+      ar[0][i] = ar[1][i] = ar[2][i] = 0.0f;
+    }
+    for (int k = 0; k < S; ++k) {
+      const float fk = (float)k + 0.5f;
+      float x[3], w[8];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] = fminf(fmaxf((rel[a] + fk * stp[a]) * sc - 1.0f, -1.0f), 1.0f);
+      corner_weights(x, w);
+      float sigma = 0.0f, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sigma += w[i] * sp[i];
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          float a = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) a += w[i] * cr[ch][i];
+          col[ch] = a;
+        }
+      }
+      if (INT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) inten += w[i] * ci[i];
+      }
+      const float e = __expf(-sigma * delta);
+      const float wgt = T * (1.0f - e);
+      const float Tn = T * e;
+      const float tk = ti + fk * delta;
+      float dtau = gOT;
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          PC[ch] += wgt * col[ch];
+          dtau += gC[ch] * (Tn * col[ch] - (Cs[ch] - PC[ch]));
+        }
+      }
+      PD += wgt * tk;
+      dtau += gD * (Tn * tk - (Ds - PD));
+      if (INT) {
+        PI += wgt * inten;
+        dtau += gI * (Tn * inten - (Is - PI));
+      }
+      const float dsig = dtau * delta;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ag[i] += dsig * w[i];
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float gw = gC[ch] * wgt;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) ar[ch][i] += gw * w[i];
+        }
+      }
+      if (INT) {
+        const float gw = gI * wgt;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ai[i] += gw * w[i];
+      }
+      T = Tn;
+    }
+    if (b.dgeo) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) unsafeAtomicAdd(&b.dgeo[(int64_t)v * 8 + i], ag[i] * sigmoid_f(zg[i]));
+    }
+    if (RGB && b.drgb) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          unsafeAtomicAdd(&b.drgb[(int64_t)v * 24 + ch * 8 + i], ar[ch][i] * cr[ch][i] * (1.0f - cr[ch][i]));
+    }
+    if (INT && b.dint) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) unsafeAtomicAdd(&b.dint[(int64_t)v * 8 + i], ai[i] * ci[i] * (1.0f - ci[i]));
+    }
+    return ++count < n_stop;
+  });
+}
+
+template <int FIELD>
+hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stream) {
+  const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
+  if (rgb && in) render_kernel<FIELD, true, true><<<blocks, kThreads, 0, stream>>>(p);
+  else if (rgb) render_kernel<FIELD, true, false><<<blocks, kThreads, 0, stream>>>(p);
+  else if (in) render_kernel<FIELD, false, true><<<blocks, kThreads, 0, stream>>>(p);
+  else render_kernel<FIELD, false, false><<<blocks, kThreads, 0, stream>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
+  const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;
+  if (threads <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
+  if (field == SALF_FIELD_PAPER) return launch_field<SALF_FIELD_PAPER>(p, blocks, stream);
+  return launch_field<SALF_FIELD_CORNER>(p, blocks, stream);
+}
+
+hipError_t launch_backward(const BackwardParams& b, hipStream_t stream) {
+  const RenderParams& p = b.fwd;
+  const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;
+  if (threads <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
+  const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
+  if (rgb && in) backward_kernel<true, true><<<blocks, kThreads, 0, stream>>>(b);
+  else if (rgb) backward_kernel<true, false><<<blocks, kThreads, 0, stream>>>(b);
+  else if (in) backward_kernel<false, true><<<blocks, kThreads, 0, stream>>>(b);
+  else backward_kernel<false, false><<<blocks, kThreads, 0, stream>>>(b);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int32_t* counts, int32_t* ids,
+                        float* t_in, float* t_out, hipStream_t stream) {
+  if (r.n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((r.n + kThreads - 1) / kThreads);
+  trace_kernel<<<blocks, kThreads, 0, stream>>>(s, r, max_hits, counts, ids, t_in, t_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uint8_t* valid, hipStream_t stream) {
+  const int64_t n = (int64_t)s.width * s.height;
+  if (n <= 0) return hipSuccess;
+  raygen_kernel<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, stream>>>(s, o, d, t, valid);
+  return hipGetLastError();
+}
+
+}  // namespace salf

@@ -1,0 +1,237 @@
+// Acceleration-structure build on the GPU: a dense root grid whose occupied cells hold either a
+// level-0 voxel or an 8-ary octree, whose non-leaf nodes point to their 8 sub-volumes and whose
+// leaves hold "empty" or a voxel (Sec. 3.2, octree ray casting).
+//
+// Build, one thread per voxel, four kernels:
+//   1. fill: root grid and node children <- empty, hash keys <- unused
+//   2. insert: validate each voxel (level and coordinates in range) and insert the keys of its
+//      ancestors (depth m = 0 .. l-1, coordinates >> (l - m)) into an open-addressing hash set
+//   3. number: every occupied hash slot receives a node index
+//   4. link: write each ancestor's index into its parent's child slot (or the root grid) and the
+//      voxel's leaf code into its own slot, all by compare-and-swap from "empty".  Two voxels that
+//      overlap or repeat make two different values compete for one slot; the loser is reported.
+#include "internal.hpp"
+
+namespace salf {
+namespace {
+
+constexpr uint64_t kNoKey = ~0ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t node_key(int depth, int32_t x, int32_t y, int32_t z) {
+  return ((uint64_t)depth << 60) | ((uint64_t)x << 40) | ((uint64_t)y << 20) | (uint64_t)z;
+}
+
+__global__ void fill_i32(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void init_counters(BuildCounters* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->error_bits = 0;
+    c->first_bad = 0x7fffffff;
+    c->n_nodes = 0;
+    c->n_occupied = 0;
+  }
+}
+
+struct BuildArgs {
+  const int32_t* vox;
+  int64_t n;
+  int32_t dims[3];
+  int32_t K;
+  int32_t* root;
+  int32_t* nodes;
+  uint64_t* hkeys;
+  int32_t* hvals;
+  int64_t hcap;
+  int64_t node_cap;
+  BuildCounters* cnt;
+};
+
+__device__ __forceinline__ void report(BuildCounters* c, int bit, int32_t v) {
+  atomicOr(&c->error_bits, bit);
+  atomicMin(&c->first_bad, v);
+}
+
+__device__ __forceinline__ bool voxel_ok(const BuildArgs& a, int32_t l, int32_t i, int32_t j, int32_t k) {
+  if (l < 0 || l > a.K) return false;
+  return i >= 0 && j >= 0 && k >= 0 && i < (a.dims[0] << l) && j < (a.dims[1] << l) && k < (a.dims[2] << l);
+}
+
+__device__ bool hash_insert(const BuildArgs& a, uint64_t key) {
+  uint64_t h = mix64(key) & (uint64_t)(a.hcap - 1);
+  for (int64_t probe = 0; probe < a.hcap; ++probe) {
+    const uint64_t prev = atomicCAS((unsigned long long*)&a.hkeys[h], (unsigned long long)kNoKey,
+                                    (unsigned long long)key);
+    if (prev == kNoKey || prev == key) return true;
+    h = (h + 1) & (uint64_t)(a.hcap - 1);
+  }
+  return false;
+}
+
+__device__ int32_t hash_find(const BuildArgs& a, uint64_t key) {
+  uint64_t h = mix64(key) & (uint64_t)(a.hcap - 1);
+  for (int64_t probe = 0; probe < a.hcap; ++probe) {
+    const uint64_t k = a.hkeys[h];
+    if (k == key) return a.hvals[h];
+    if (k == kNoKey) return -1;
+    h = (h + 1) & (uint64_t)(a.hcap - 1);
+  }
+  return -1;
+}
+
+__global__ void insert_kernel(BuildArgs a) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int4 q = reinterpret_cast<const int4*>(a.vox)[v];
+  const int32_t l = q.x;
+  if (!voxel_ok(a, l, q.y, q.z, q.w)) {
+    report(a.cnt, 1, (int32_t)v);
+    return;
+  }
+  for (int m = 0; m < l; ++m) {
+    const int sh = l - m;
+    if (!hash_insert(a, node_key(m, q.y >> sh, q.z >> sh, q.w >> sh))) {
+      report(a.cnt, 4, (int32_t)v);
+      return;
+    }
+  }
+}
+
+__global__ void number_kernel(BuildArgs a) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h >= a.hcap) return;
+  if (a.hkeys[h] != kNoKey) {
+    const int32_t id = atomicAdd(&a.cnt->n_nodes, 1);
+    a.hvals[h] = (id < a.node_cap) ? id : -1;
+    if (id >= a.node_cap) report(a.cnt, 4, 0);
+  }
+}
+
+__device__ __forceinline__ bool claim(int32_t* slot, int32_t value) {
+  const int32_t old = atomicCAS(slot, kEmpty, value);
+  return old == kEmpty || old == value;
+}
+
+__global__ void link_kernel(BuildArgs a) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int4 q = reinterpret_cast<const int4*>(a.vox)[v];
+  const int32_t l = q.x;
+  if (!voxel_ok(a, l, q.y, q.z, q.w)) return;
+  int32_t parent = -1;  // node index of the depth m-1 ancestor
+  for (int m = 0; m <= l; ++m) {
+    const int sh = l - m;
+    const int32_t x = q.y >> sh, y = q.z >> sh, z = q.w >> sh;
+    int32_t value;
+    if (m == l) {
+      value = leaf_code((int32_t)v);
+    } else {
+      value = hash_find(a, node_key(m, x, y, z));
+      if (value < 0) {
+        report(a.cnt, 4, (int32_t)v);
+        return;
+      }
+    }
+    int32_t* slot;
+    if (m == 0) {
+      slot = &a.root[((int64_t)z * a.dims[1] + y) * a.dims[0] + x];
+    } else {
+      slot = &a.nodes[(int64_t)parent * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2))];
+    }
+    if (!claim(slot, value)) {
+      report(a.cnt, 2, (int32_t)v);
+      return;
+    }
+    parent = value;
+  }
+}
+
+__global__ void count_roots(const int32_t* root, int64_t n, BuildCounters* c) {
+  int32_t mine = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mine += root[i] != kEmpty;
+  if (mine) atomicAdd(&c->n_occupied, mine);
+}
+
+// one thread per item (n <= 2^31 here, so the grid fits in gridDim.x)
+inline unsigned blocks_for(int64_t n, int threads) {
+  const int64_t b = (n + threads - 1) / threads;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
+  const int K = d.max_level;
+  int64_t n_root = (int64_t)d.root_dims[0] * d.root_dims[1] * d.root_dims[2];
+  // every voxel adds at most K ancestors; no depth can hold more nodes than it has cells
+  int64_t geo_cap = 0, cells = n_root;
+  for (int m = 0; m < K; ++m) {
+    geo_cap += cells;
+    if (geo_cap > ((int64_t)1 << 40)) break;
+    cells *= 8;
+  }
+  int64_t node_cap = n * (int64_t)K;
+  if (geo_cap < node_cap) node_cap = geo_cap;
+  int64_t hcap = 1024;
+  while (hcap < 2 * node_cap) hcap <<= 1;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  L->n_root = n_root;
+  L->node_cap = node_cap;
+  L->hash_cap = hcap;
+  L->root_off = off;
+  off = up(off + (size_t)n_root * 4);
+  L->nodes_off = off;
+  off = up(off + (size_t)node_cap * 32);
+  L->hkeys_off = off;
+  off = up(off + (size_t)hcap * 8);
+  L->hvals_off = off;
+  off = up(off + (size_t)hcap * 4);
+  L->counters_off = off;
+  off = up(off + sizeof(BuildCounters));
+  L->total = off;
+  return true;
+}
+
+hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t* voxels, const SceneLayout& L,
+                              void* ws, hipStream_t stream) {
+  char* base = (char*)ws;
+  BuildArgs a;
+  a.vox = voxels;
+  a.n = n;
+  for (int i = 0; i < 3; ++i) a.dims[i] = d.root_dims[i];
+  a.K = d.max_level;
+  a.root = (int32_t*)(base + L.root_off);
+  a.nodes = (int32_t*)(base + L.nodes_off);
+  a.hkeys = (uint64_t*)(base + L.hkeys_off);
+  a.hvals = (int32_t*)(base + L.hvals_off);
+  a.hcap = L.hash_cap;
+  a.node_cap = L.node_cap;
+  a.cnt = (BuildCounters*)(base + L.counters_off);
+  const int T = 256;
+  fill_i32<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.root, kEmpty, L.n_root);
+  if (L.node_cap > 0) fill_i32<<<blocks_for(L.node_cap * 8, T), T, 0, stream>>>(a.nodes, kEmpty, L.node_cap * 8);
+  fill_u64<<<blocks_for(L.hash_cap, T), T, 0, stream>>>(a.hkeys, kNoKey, L.hash_cap);
+  init_counters<<<1, 64, 0, stream>>>(a.cnt);
+  if (n > 0) insert_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
+  number_kernel<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
+  if (n > 0) link_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
+  count_roots<<<blocks_for(L.n_root, T) > 1024 ? 1024 : blocks_for(L.n_root, T), T, 0, stream>>>(a.root, L.n_root,
+                                                                                                  a.cnt);
+  return hipGetLastError();
+}
+
+}  // namespace salf

@@ -1,0 +1,128 @@
+"""The C ABI library without a GPU: it loads, exports every declared entry point, its structs
+have the layout the Python binding assumes, and its host-only calls validate arguments."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "salf.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_18713_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(salf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(L):
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, f"{name} has no Python signature"
+    assert lib.salf_abi_version() == 1
+
+
+def test_struct_layout_matches_the_header(L):
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "salf.h"
+int main(void) {
+  printf("SceneDesc %zu %zu %zu\n", sizeof(salf_scene_desc), offsetof(salf_scene_desc, root_dims), offsetof(salf_scene_desc, reserved));
+  printf("SceneStats %zu %zu\n", sizeof(salf_scene_stats), offsetof(salf_scene_stats, workspace_bytes));
+  printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
+  printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
+  printf("RenderOpts %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, reserved));
+  printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
+  printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "l.c")
+        exe = os.path.join(td, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {ln.split()[0]: [int(x) for x in ln.split()[1:]] for ln in out if ln.strip()}
+    S = L
+    want = {
+        "SceneDesc": [C.sizeof(S.SceneDesc), S.SceneDesc.root_dims.offset, S.SceneDesc.reserved.offset],
+        "SceneStats": [C.sizeof(S.SceneStats), S.SceneStats.workspace_bytes.offset],
+        "Sensor": [C.sizeof(S.Sensor), S.Sensor.R0.offset, S.Sensor.t_far.offset],
+        "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
+        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.reserved.offset],
+        "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
+        "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
+    }
+    assert got == want
+
+
+def _desc(L, dims=(4, 4, 4), K=2, s0=1.0, field=0):
+    d = L.SceneDesc()
+    d.origin[:] = [0.0, 0.0, 0.0]
+    d.root_size = s0
+    d.root_dims[:] = list(dims)
+    d.max_level = K
+    d.field = field
+    d.reserved = 0
+    return d
+
+
+def test_workspace_size_host_logic(L):
+    lib = L.lib()
+    n = C.c_size_t()
+    assert lib.salf_scene_workspace_size(C.byref(_desc(L)), 100, C.byref(n)) == 0
+    small = n.value
+    assert lib.salf_scene_workspace_size(C.byref(_desc(L)), 10000, C.byref(n)) == 0
+    assert n.value > small
+    # a K = 0 scene needs only the root grid and counters
+    assert lib.salf_scene_workspace_size(C.byref(_desc(L, dims=(32, 32, 32), K=0)), 4096, C.byref(n)) == 0
+    assert 32 ** 3 * 4 <= n.value < 32 ** 3 * 4 + 64 * 1024
+    # invalid descriptions
+    for bad in (_desc(L, K=9), _desc(L, s0=0.0), _desc(L, s0=math.nan), _desc(L, dims=(0, 4, 4)),
+                _desc(L, dims=(1 << 17, 4, 4), K=4), _desc(L, field=7)):
+        assert lib.salf_scene_workspace_size(C.byref(bad), 10, C.byref(n)) == -1
+        assert len(lib.salf_last_error()) > 0
+    assert lib.salf_scene_workspace_size(C.byref(_desc(L)), -1, C.byref(n)) == -1
+
+
+def test_sensor_ray_count_host_logic(L):
+    from paper_2507_18713_amd.api import sensor_struct
+    import synth
+    lib = L.lib()
+    n = C.c_int64()
+    assert lib.salf_sensor_ray_count(C.byref(sensor_struct(synth.config1_camera())), C.byref(n)) == 0
+    assert n.value == 1920 * 1080
+    assert lib.salf_sensor_ray_count(C.byref(sensor_struct(synth.config2_lidar())), C.byref(n)) == 0
+    assert n.value == 131072
+    bad = synth.config1_camera()
+    bad["width"] = 0
+    assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
+    bad = dict(synth.config1_camera(), model=5)
+    assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
+    bad = dict(synth.config1_camera(), t_near=2.0, t_far=1.0)
+    assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
+
+
+def test_null_arguments_are_rejected(L):
+    lib = L.lib()
+    assert lib.salf_create(0, None) == -1
+    assert lib.salf_destroy(None) == -1
+    assert lib.salf_sync(None, None) == -1
+    assert lib.salf_render(None, 0, None, None, None, None, None) == -1
+    assert lib.salf_scene_get_stats(None, 0, None) == -1

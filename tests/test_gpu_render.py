@@ -1,0 +1,290 @@
+"""GPU parity of the HIP renderer against the CPU oracle (all calls go through the C ABI).
+
+Bar: hit lists bit-exact (ids, t_in, t_out); colour, opacity and intensity within 1e-4 absolute;
+depth within 1e-3 m; n_hits equal.  Rays fed to both sides come from the oracle's sensor models
+(float64, rounded to float32) or from the seeded generators; nothing the GPU computes is used
+as an oracle input.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle.render import RenderOpts
+
+pytestmark = pytest.mark.gpu
+
+TOL_C, TOL_D = 1e-4, 1e-3
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def salf():
+    import paper_2507_18713_amd as m
+    return m
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev(), dtype=dtype)
+
+
+def check_hits(salf, scene, ps, o, d, max_hits=256, t_near=0.0, t_far=math.inf, idx=None):
+    """GPU trace_hits vs the oracle's brute force, bit for bit."""
+    idx = np.arange(o.shape[0]) if idx is None else idx
+    counts, ids, ti, to = salf.trace_hits(scene, to_dev(o[idx]), to_dev(d[idx]), max_hits, t_near, t_far)
+    counts, ids, ti, to = (x.cpu().numpy() for x in (counts, ids, ti, to))
+    total = 0
+    for q, r in enumerate(idx):
+        e_ids, e_ti, e_to = oracle.hit_list(ps, o[r], d[r], t_near, t_far)
+        assert counts[q] == e_ids.size, (r, counts[q], e_ids.size)
+        k = min(e_ids.size, max_hits)
+        assert np.array_equal(ids[q, :k], e_ids[:k]), r
+        assert np.array_equal(ti[q, :k].view(np.uint32), e_ti[:k].view(np.uint32)), r
+        assert np.array_equal(to[q, :k].view(np.uint32), e_to[:k].view(np.uint32)), r
+        total += e_ids.size
+    return total
+
+
+def check_outputs(got, ref, idx=None, keys=("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")):
+    for k in keys:
+        if k not in got:
+            continue
+        g = got[k].cpu().numpy()
+        g = g if idx is None else g[idx]
+        e = ref[k]
+        if k == "n_hits":
+            assert np.array_equal(g, e), k
+            continue
+        tol = TOL_D if k == "depth" else TOL_C
+        err = np.max(np.abs(g.astype(np.float64) - e)) if g.size else 0.0
+        assert err <= tol, (k, err)
+
+
+def oracle_rays(sensor):
+    o, d, t, valid = oracle.sensor_rays(sensor)
+    return o.astype(F32), d.astype(F32), valid
+
+
+# ------------------------------------------------------------------ tiny scene (config 0)
+@pytest.mark.parametrize("S", [1, 4])
+def test_tiny_scene_all_rays(salf, S):
+    data = synth.config0_scene()
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev())
+    o, d, _ = oracle_rays(synth.config0_camera())
+    n_hit = check_hits(salf, scene, ps, o, d)
+    assert n_hit > 5000
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S, outputs=outs, image_width=64)
+    ref = oracle.render_rays(ps, o, d, RenderOpts(samples=S))
+    check_outputs(got, ref)
+    # linear (untiled) launch gives the same bits
+    lin = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S, outputs=outs)
+    for k in outs:
+        assert torch.equal(lin[k], got[k]), k
+
+
+@pytest.mark.parametrize("seed,K", [(31, 1), (32, 2), (33, 3)])
+def test_adaptive_scenes_random_rays(salf, seed, K):
+    data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=K)
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev())
+    lo, hi = data.origin, data.origin + data.root_dims * data.root_size
+    o, d = synth.random_rays(seed, 700, lo, hi)
+    # axis-parallel rays, rays on faces and rays from inside a voxel exercise the rule's corners
+    d[:6] = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0], [0, 0, -1]], F32)
+    o[6:12] = (data.origin + np.array([1.0, 1.0, 1.0]) * data.root_size).astype(F32)
+    check_hits(salf, scene, ps, o, d)
+    bg = (0.2, 0.3, 0.4)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg,
+                      outputs=("rgb", "depth", "opacity", "intensity", "t_end", "n_hits"))
+    check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(background=bg)))
+    st = scene.stats()
+    assert st["n_voxels"] == data.n and st["n_nodes"] > 0
+
+
+def test_paper_field_forward(salf):
+    data = synth.random_scene(41, root_dims=(5, 4, 3), max_level=2)
+    # Eq. 1-2 parameters: bias N(0,1), slopes N(0, 0.5^2), SH DC N(0,1), SH higher N(0, 0.25^2)
+    rng = np.random.default_rng(42)
+    n = data.n
+    geo = np.zeros((n, 8), F32)
+    geo[:, :3] = rng.normal(0, 0.5, (n, 3))
+    geo[:, 3] = rng.normal(0, 1, n)
+    rgb = np.zeros((n, 3, 8), F32)
+    rgb[:, :, :3] = rng.normal(0, 0.5, (n, 3, 3))
+    rgb[:, :, 3] = rng.normal(0, 1, (n, 3))
+    rgb[:, :, 4:7] = rng.normal(0, 0.25, (n, 3, 3))
+    ity = np.zeros((n, 8), F32)
+    ity[:, :4] = rng.normal(0, 0.5, (n, 4))
+    data.z_geo, data.z_rgb, data.z_int = geo, rgb, ity
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    o, d = synth.random_rays(43, 600, data.origin, data.origin + data.root_dims * data.root_size)
+    for S in (1, 4):
+        got = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S,
+                          outputs=("rgb", "depth", "opacity", "intensity", "n_hits"))
+        check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(samples=S, field="paper")))
+
+
+def test_tiny_scene_paper_field_camera(salf):
+    data = synth.config0_scene()
+    rng = np.random.default_rng(44)
+    data.z_geo = np.concatenate([rng.normal(0, 0.5, (data.n, 3)), rng.normal(0, 1, (data.n, 1)),
+                                 np.zeros((data.n, 4))], 1).astype(F32)
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    o, d, _ = oracle_rays(synth.config0_camera())
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), image_width=64, outputs=("rgb", "depth", "opacity"))
+    check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(field="paper")))
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_scene_and_misses(salf):
+    empty = synth.SceneData(origin=np.zeros(3), root_size=1.0, root_dims=np.array([3, 3, 3]), max_level=2,
+                            voxels=np.zeros((0, 4), np.int32), z_geo=np.zeros((0, 8), F32),
+                            z_rgb=np.zeros((0, 3, 8), F32), z_int=np.zeros((0, 8), F32))
+    scene = salf.Scene.from_data(empty, device=dev())
+    o, d = synth.random_rays(1, 100, (0, 0, 0), (3, 3, 3))
+    bg = (0.25, 0.5, 0.75)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg, outputs=("rgb", "depth", "opacity", "n_hits"))
+    assert torch.all(got["rgb"].cpu() == torch.tensor(bg)) and torch.all(got["opacity"] == 0)
+    assert torch.all(got["depth"] == 0) and torch.all(got["n_hits"] == 0)
+    # zero rays
+    z = torch.zeros((0, 3), device=dev())
+    got = salf.render(scene, o=z, d=z, outputs=("rgb",))
+    assert got["rgb"].shape == (0, 3)
+
+
+def test_invalid_rays_render_background(salf):
+    data = synth.random_scene(51)
+    scene = salf.Scene.from_data(data, device=dev())
+    o = np.zeros((4, 3), F32)
+    d = np.array([[0, 0, 0], [np.nan, 0, 1], [1, 0, np.inf], [0.0, 0.0, 1e-45]], F32)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), background=(1, 0, 0), outputs=("rgb", "opacity", "n_hits"))
+    assert torch.all(got["n_hits"] == 0) and torch.all(got["opacity"] == 0)
+    assert torch.all(got["rgb"].cpu() == torch.tensor([1.0, 0.0, 0.0]))
+
+
+def test_near_far_clipping(salf):
+    data = synth.random_scene(52, root_dims=(6, 5, 4), max_level=2)
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev())
+    o, d = synth.random_rays(53, 500, data.origin, data.origin + data.root_dims * data.root_size)
+    check_hits(salf, scene, ps, o, d, t_near=1.5, t_far=4.0)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), t_near=1.5, t_far=4.0,
+                      outputs=("rgb", "depth", "opacity", "n_hits"))
+    check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(t_near=1.5, t_far=4.0)))
+
+
+def test_early_termination_and_max_samples(salf):
+    data = synth.random_scene(54, root_dims=(6, 5, 4), max_level=1, fill=0.9)
+    data.z_geo = (data.z_geo + 3.0).astype(F32)          # dense: most rays stop early
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev())
+    o, d = synth.random_rays(55, 500, data.origin, data.origin + data.root_dims * data.root_size)
+    for S, tmin in ((4, 1e-6), (4, 1e-2), (32, 1e-6), (3, 0.0)):
+        got = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S, t_min=tmin,
+                          outputs=("rgb", "depth", "opacity", "t_end", "n_hits"))
+        ref = oracle.render_rays(ps, o, d, RenderOpts(samples=S, t_min=tmin))
+        check_outputs(got, ref)
+        if tmin > 0:
+            full = oracle.render_rays(ps, o, d, RenderOpts(samples=S, t_min=0.0))
+            assert np.sum(ref["n_hits"] < full["n_hits"]) > 20
+
+
+def test_upload_order_only_renames(salf):
+    data = synth.random_scene(56)
+    perm = np.random.default_rng(57).permutation(data.n)
+    a = salf.Scene.from_data(data, device=dev())
+    b = salf.Scene.from_data(data.permuted(perm), device=dev())
+    o, d = synth.random_rays(58, 400, data.origin, data.origin + data.root_dims * data.root_size)
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    ra = salf.render(a, o=to_dev(o), d=to_dev(d), outputs=outs)
+    rb = salf.render(b, o=to_dev(o), d=to_dev(d), outputs=outs)
+    for k in outs:
+        assert torch.equal(ra[k], rb[k]), k
+    ca, ia, _, _ = salf.trace_hits(a, to_dev(o), to_dev(d), 128)
+    cb, ib, _, _ = salf.trace_hits(b, to_dev(o), to_dev(d), 128)
+    ib = ib.cpu().numpy()
+    mapped = np.where(ib >= 0, perm[np.maximum(ib, 0)], -1)
+    assert torch.equal(ca, cb) and np.array_equal(ia.cpu().numpy(), mapped)
+
+
+def test_scene_validation_errors(salf):
+    data = synth.random_scene(59, max_level=2)
+    bad = data.permuted(np.arange(data.n))
+    bad.voxels = np.concatenate([bad.voxels, bad.voxels[3:4]], 0)          # duplicate
+    bad.z_geo = np.concatenate([bad.z_geo, bad.z_geo[:1]], 0)
+    bad.z_rgb = np.concatenate([bad.z_rgb, bad.z_rgb[:1]], 0)
+    bad.z_int = np.concatenate([bad.z_int, bad.z_int[:1]], 0)
+    with pytest.raises(salf.SalfError, match="overlaps or repeats"):
+        salf.Scene.from_data(bad, device=dev())
+    # a voxel containing another
+    lo_i, _ = data.finest_bounds()
+    v = int(np.nonzero(data.voxels[:, 0] == 2)[0][0])
+    par = data.voxels[v].copy()
+    par[0] = 1
+    par[1:] //= 2
+    bad.voxels = np.concatenate([data.voxels, par[None]], 0)
+    with pytest.raises(salf.SalfError, match="overlaps or repeats"):
+        salf.Scene.from_data(bad, device=dev())
+    # out of range
+    bad.voxels = np.concatenate([data.voxels, np.array([[0, 99, 0, 0]], np.int32)], 0)
+    with pytest.raises(salf.SalfError, match=f"voxel {data.n} "):
+        salf.Scene.from_data(bad, device=dev())
+
+
+# ------------------------------------------------------------------ sensors
+def _ray_errors(gpu, o64, d64, valid):
+    go, gd = gpu["o"].cpu().numpy().astype(np.float64), gpu["d"].cpu().numpy().astype(np.float64)
+    gv = gpu["valid"].cpu().numpy().astype(bool)
+    assert np.array_equal(gv, valid)
+    ang = np.arccos(np.clip(np.sum(gd[valid] * d64[valid], 1) / np.linalg.norm(gd[valid], axis=1), -1, 1))
+    return float(np.max(np.abs(go - o64))), float(np.max(ang)) if ang.size else 0.0
+
+
+@pytest.mark.parametrize("name", ["pinhole", "pinhole_rs", "fisheye_rs", "lidar"])
+def test_sensor_rays_match_float64_models(salf, name):
+    if name == "pinhole":
+        s = synth.config1_camera()
+    elif name == "pinhole_rs":
+        s = synth.pinhole(1920, 1080, 70.0, synth.yaw_pitch_camera(60, -3), (10, -1.75, 1.6), dt_line=30e-6,
+                          v=(10, 0, 0), w=(0, 0, 0.3))
+    elif name == "fisheye_rs":
+        s = synth.fisheye_equidistant(1280, 960, 190.0, synth.yaw_pitch_camera(90, 0), (10, -1.75, 1.6),
+                                      dt_line=30e-6, v=(10, 0, 0), w=(0, 0, 0.3))
+    else:
+        s = synth.config2_lidar()
+    gpu = salf.generate_rays(s, device=dev())
+    o, d, t, valid = oracle.sensor_rays(s)
+    eo, ed = _ray_errors(gpu, o, d, valid)
+    assert eo <= 1e-5 and ed <= 1e-6, (eo, ed)
+    assert np.max(np.abs(gpu["t"].cpu().numpy() - t)) <= 1e-6
+    if name == "fisheye_rs":
+        assert int(valid.sum()) == 1101128
+
+
+def test_fused_sensor_render_equals_explicit_rays(salf):
+    data = synth.random_scene(61, root_dims=(6, 5, 4), max_level=2)
+    scene = salf.Scene.from_data(data, device=dev())
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    for s in (synth.pinhole(37, 29, 80.0, synth.look_at((8, -7, 5), (0, 0, 0)), (8, -7, 5), dt_line=1e-3,
+                            v=(1, 2, 0), w=(0, 0.5, 0.2)),
+              synth.fisheye_equidistant(40, 30, 190.0, synth.look_at((0.1, 0.2, 0.3), (1, 0, 0)), (0.1, 0.2, 0.3)),
+              synth.lidar_spinning(16, 100, -25, 15, np.eye(3), (0.5, -0.4, 0.3), 0.1, v=(10, 0, 0))):
+        fused = salf.render(scene, sensor=s, outputs=outs)
+        r = salf.generate_rays(s, device=dev())
+        expl = salf.render(scene, o=r["o"], d=r["d"], outputs=outs, image_width=s["width"])
+        valid = r["valid"].bool()
+        for k in outs:
+            a, b = fused[k], expl[k]
+            assert torch.equal(a[valid], b[valid]), k
+        assert torch.all(fused["opacity"][~valid] == 0)
