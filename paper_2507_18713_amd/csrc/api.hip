@@ -260,6 +260,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   SceneView& v = sc.view;
   v.root = (const int32_t*)((char*)d_workspace + L.root_off);
   v.nodes = (const int32_t*)((char*)d_workspace + L.nodes_off);
+  v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
   v.geo = d_geo;
   v.rgb = d_rgb;
   v.inten = d_int;

@@ -1,9 +1,9 @@
 // Device-side building blocks of the renderer (gfx950, wave64).
 //
 //  * the FP32 ray/voxel interval rule in the finest-grid frame (the hit definition of salf.h);
-//  * front-to-back traversal of the occupied voxels of a ray: a root-grid walk plus an octree
-//    descent that skips empty space (Sec. 3.2, octree ray casting), driven by a single running
-//    parameter t so that every voxel is reported with exactly the interval the rule defines;
+//  * front-to-back traversal of the occupied voxels of a ray: a root-grid walk that jumps over
+//    empty space plus an octree walk with a per-lane node stack (Sec. 3.2, octree ray casting),
+//    shaped so that the lanes of a wave report their hits at one convergent point;
 //  * sensor ray generation (pinhole, equidistant fisheye, spinning LiDAR, rolling shutter);
 //  * local field evaluation (corner-interpolated mode, and Eq. 1-2).
 #pragma once
@@ -27,6 +27,8 @@ struct SceneView {
   const float* geo;      // [N][8]
   const float* rgb;      // [N][3][8] or null
   const float* inten;    // [N][8] or null
+  const uint8_t* skip;   // [Dz][Dy][Dx] Chebyshev distance (in root cells, capped) to the nearest
+                         // occupied root cell; 0 = occupied.  Null: no empty-space skipping.
   int32_t dims[3];       // root cells per axis
   int32_t K;             // finest level
   float org32[3];        // grid origin, FP32
@@ -45,10 +47,9 @@ __device__ __forceinline__ float plane_t(float P, float og, float inv) {
 
 // Per-ray grid-frame state.
 struct RayFrame {
-  float og[3], inv[3];
-  int par;          // bit a set: axis a is parallel
-  double ogd[3];    // FP64 grid-frame origin and direction for sample positions
-  double dgd[3];
+  float og[3], dg[3], inv[3];
+  float o[3], d[3];  // the ray as given (FP32); sample positions are formed from it in FP64
+  int par;           // bit a set: axis a is parallel
   float t_near, t_far;
   bool valid;
 };
@@ -59,14 +60,16 @@ __device__ inline RayFrame make_frame(const SceneView& s, const float o[3], cons
   RayFrame f;
   f.par = 0;
   bool finite = true;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     finite = finite && isfinite(o[a]) && isfinite(d[a]);
+    f.o[a] = o[a];
+    f.d[a] = d[a];
     f.og[a] = (o[a] - s.org32[a]) * s.gs32;
     const float dg = d[a] * s.gs32;
+    f.dg[a] = dg;
     f.inv[a] = 1.0f / dg;  // correctly rounded division (HIP default)
     if (dg == 0.0f || isinf(f.inv[a])) f.par |= 1 << a;
-    f.ogd[a] = ((double)o[a] - s.org[a]) * s.gs;
-    f.dgd[a] = (double)d[a] * s.gs;
   }
   f.valid = finite && f.par != 7;
   f.t_near = t_near;
@@ -97,133 +100,251 @@ __device__ __forceinline__ bool box_interval(const RayFrame& f, const int32_t lo
 }
 
 // ----------------------------------------------------------------------------- traversal
-// Calls visit(voxel, lo[3], size, t_in, t_out) for every voxel the ray hits, in increasing
-// t_in, until visit returns false.  lo/size are in finest cells.
-//
-// The walk keeps a running parameter t.  At root level it maintains, per axis, the root-cell
-// index whose slab [t_a(entry plane), t_a(exit plane)) contains t; inside an occupied root
-// cell it descends, per level, to the child whose per-axis half-open slabs contain t (compare
-// t with the FP32 crossing of the mid plane).  Because every slab bound is the same FP32
-// plane crossing the rule uses, the leaf found contains t in the rule's sense, its t_in is t,
-// and its t_out (> t) is where the walk continues; voxels are found exactly once and none is
-// missed.  Each step strictly increases t, and a step budget bounds the loop regardless.
-template <typename Visit>
-__device__ inline void traverse(const SceneView& s, const RayFrame& f, Visit&& visit) {
-  if (!f.valid) return;
-  const int K = s.K;
-  int32_t glo[3] = {0, 0, 0};
-  int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
-  float t_enter, t_exit;
-  if (!box_interval(f, glo, ghi, t_enter, t_exit)) return;
-  if (!(t_enter < t_exit)) return;
+// Root cell index of a non-parallel axis whose half-open slab contains t under the rule, and
+// the crossing where the ray leaves it.  The position guess is corrected against the rule's
+// own plane crossings, which are monotone in the plane.
+__device__ __forceinline__ void locate_axis(const RayFrame& f, int a, float t, int D, int K, int& k, float& nxt) {
+  const float pos = f.og[a] + t * f.dg[a];
+  int c = (int)floorf(pos) >> K;
+  c = c < 0 ? 0 : (c >= D ? D - 1 : c);
+  const float og = f.og[a], inv = f.inv[a];
+  if (inv > 0.0f) {
+    while (c > 0 && plane_t((float)(c << K), og, inv) > t) --c;
+    while (c < D - 1 && plane_t((float)((c + 1) << K), og, inv) <= t) ++c;
+    nxt = plane_t((float)((c + 1) << K), og, inv);
+  } else {
+    while (c < D - 1 && plane_t((float)((c + 1) << K), og, inv) > t) ++c;
+    while (c > 0 && plane_t((float)(c << K), og, inv) <= t) --c;
+    nxt = plane_t((float)(c << K), og, inv);
+  }
+  k = c;
+}
 
-  int k[3], step[3];
-  float nxt[3];
+// Where the ray leaves the box [lo, lo + size) (finest cells): the smallest exit-plane crossing.
+__device__ __forceinline__ float box_exit(const RayFrame& f, const int32_t lo[3], int32_t size) {
+  float to = f.t_far;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int D = s.dims[a];
-    if (f.par & (1 << a)) {
-      int c = (int)f.og[a] >> K;  // og in [0, D << K) here
-      k[a] = c < 0 ? 0 : (c >= D ? D - 1 : c);
-      step[a] = 0;
-      nxt[a] = INFINITY;
-      continue;
-    }
-    // guess the cell at t_enter, then correct it against the rule's plane crossings
-    const float pos = f.og[a] + t_enter * (1.0f / f.inv[a]);
-    int c = (int)floorf(pos) >> K;
-    c = c < 0 ? 0 : (c >= D ? D - 1 : c);
-    if (f.inv[a] > 0.0f) {
-      while (c > 0 && plane_t((float)(c << K), f.og[a], f.inv[a]) > t_enter) --c;
-      while (c < D - 1 && plane_t((float)((c + 1) << K), f.og[a], f.inv[a]) <= t_enter) ++c;
-      step[a] = 1;
-      nxt[a] = plane_t((float)((c + 1) << K), f.og[a], f.inv[a]);
-    } else {
-      while (c < D - 1 && plane_t((float)((c + 1) << K), f.og[a], f.inv[a]) > t_enter) ++c;
-      while (c > 0 && plane_t((float)(c << K), f.og[a], f.inv[a]) <= t_enter) --c;
-      step[a] = -1;
-      nxt[a] = plane_t((float)(c << K), f.og[a], f.inv[a]);
-    }
-    k[a] = c;
+    if (f.par & (1 << a)) continue;
+    const int32_t P = (f.inv[a] > 0.0f) ? lo[a] + size : lo[a];
+    to = fminf(to, plane_t((float)P, f.og[a], f.inv[a]));
   }
+  return to;
+}
 
-  int budget = 1 << 22;
-  float t = t_enter;
-  const int32_t N0 = 1 << K;
-  while (budget-- > 0) {
-    const float cell_exit = fminf(fminf(nxt[0], nxt[1]), fminf(nxt[2], t_exit));
-    const int32_t code = s.root[((int64_t)k[2] * s.dims[1] + k[1]) * s.dims[0] + k[0]];
-    if (code != kEmpty) {
-      const int32_t rlo[3] = {k[0] << K, k[1] << K, k[2] << K};
-      if (is_leaf_code(code)) {
-        const int32_t hi[3] = {rlo[0] + N0, rlo[1] + N0, rlo[2] + N0};
-        float ti, to;
-        box_interval(f, rlo, hi, ti, to);
-        if (ti < to && !visit(leaf_voxel(code), rlo, N0, ti, to)) return;
-      } else {
-        float tc = t;
-        while (tc < cell_exit && budget-- > 0) {
-          int32_t node = code, size = N0, c8 = 0, child = kEmpty;
-          int32_t lo[3] = {rlo[0], rlo[1], rlo[2]};
-          for (int depth = 0; depth < K; ++depth) {
-            const int32_t half = size >> 1;
-            c8 = 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const int32_t mid = lo[a] + half;
-              bool upper;
-              if (f.par & (1 << a)) {
-                upper = f.og[a] >= (float)mid;
-              } else {
-                const bool past = plane_t((float)mid, f.og[a], f.inv[a]) <= tc;
-                upper = (f.inv[a] > 0.0f) ? past : !past;
-              }
-              if (upper) {
-                lo[a] = mid;
-                c8 |= 1 << a;
-              }
-            }
-            size = half;
-            child = s.nodes[(int64_t)node * 8 + c8];
-            if (child >= 0) {
-              node = child;
-              child = kEmpty;  // a node below the finest level would be malformed: treat as empty
-              continue;
-            }
-            break;
-          }
-          // leaf cell [lo, lo + size): where the ray leaves it
-          float to = f.t_far;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            if (f.par & (1 << a)) continue;
-            const int32_t P = (f.inv[a] > 0.0f) ? lo[a] + size : lo[a];
-            to = fminf(to, plane_t((float)P, f.og[a], f.inv[a]));
-          }
-          if (is_leaf_code(child)) {
-            const int32_t hi[3] = {lo[0] + size, lo[1] + size, lo[2] + size};
-            float ti, tv;
-            box_interval(f, lo, hi, ti, tv);
-            if (ti < tv && !visit(leaf_voxel(child), lo, size, ti, tv)) return;
-          }
-          if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
-          tc = to;
-        }
-      }
-    }
-    if (!(cell_exit < t_exit)) return;
-    t = cell_exit;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      while (step[a] != 0 && nxt[a] <= t) {
-        k[a] += step[a];
-        if (k[a] < 0 || k[a] >= s.dims[a]) return;
-        const int32_t P = (step[a] > 0) ? (k[a] + 1) << K : k[a] << K;
-        nxt[a] = plane_t((float)P, f.og[a], f.inv[a]);
-      }
-    }
+// Root-walk state of one axis: the root-cell index holding t, the step direction (0 for a
+// parallel axis) and the crossing where the ray leaves that cell.
+struct RootAxis {
+  int k, step;
+  float nxt;
+};
+
+template <int A>
+__device__ __forceinline__ void root_axis_init(const RayFrame& f, const SceneView& s, float t, RootAxis& r) {
+  if (f.par & (1 << A)) {
+    const int c = (int)f.og[A] >> s.K;  // og in [0, D << K) for a parallel axis that hits the grid
+    r.k = c < 0 ? 0 : (c >= s.dims[A] ? s.dims[A] - 1 : c);
+    r.step = 0;
+    r.nxt = INFINITY;
+  } else {
+    locate_axis(f, A, t, s.dims[A], s.K, r.k, r.nxt);
+    r.step = f.inv[A] > 0.0f ? 1 : -1;
   }
 }
+
+// Step the axis past every cell whose exit crossing is <= t; false if the walk leaves the grid.
+template <int A>
+__device__ __forceinline__ bool root_axis_advance(const RayFrame& f, const SceneView& s, float t, RootAxis& r) {
+  if (r.step == 0) return true;
+  while (r.nxt <= t) {
+    r.k += r.step;
+    if (r.k < 0 || r.k >= s.dims[A]) return false;
+    const int32_t P = (r.step > 0) ? (r.k + 1) << s.K : r.k << s.K;
+    r.nxt = plane_t((float)P, f.og[A], f.inv[A]);
+  }
+  return true;
+}
+
+// Crossing where the ray leaves, along axis A, the cube of root cells within distance d - 1.
+template <int A>
+__device__ __forceinline__ float cube_exit(const RayFrame& f, const SceneView& s, const RootAxis& r, int d) {
+  if (r.step == 0) return INFINITY;
+  int P = (r.step > 0) ? r.k + d : r.k - (d - 1);
+  P = P < 0 ? 0 : (P > s.dims[A] ? s.dims[A] : P);
+  return plane_t((float)(P << s.K), f.og[A], f.inv[A]);
+}
+
+// Child code c8 of the 8 held in two int4 registers, by selects (no indexed register access).
+__device__ __forceinline__ int32_t pick8(const int4 a, const int4 b, int c8) {
+  const bool z = (c8 & 4) != 0, y = (c8 & 2) != 0, x = (c8 & 1) != 0;
+  const int32_t q0 = z ? b.x : a.x, q1 = z ? b.y : a.y, q2 = z ? b.z : a.z, q3 = z ? b.w : a.w;
+  const int32_t lo = x ? q1 : q0, hi = x ? q3 : q2;
+  return y ? hi : lo;
+}
+
+// One voxel hit: id, finest-cell box and the rule's interval.
+struct Hit {
+  int32_t voxel;
+  int32_t lo[3];
+  int32_t size;
+  float t_in, t_out;
+};
+
+// Sample geometry of a hit segment: the position at t_in relative to the voxel's min corner and
+// the step between samples, in finest cells, formed in FP64 from the FP32 ray and then kept in
+// FP32 (small numbers, so far-away samples keep full precision); the piece length delta and the
+// scale sc to local coordinates x = (rel + (k + 1/2) stp) sc - 1.
+__device__ __forceinline__ void segment_frame(const SceneView& s, const RayFrame& f, const Hit& h, int S,
+                                              float rel[3], float stp[3], float& delta, float& sc) {
+  const double dt = (double)h.t_out - (double)h.t_in;
+  delta = (float)(dt / S);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ogd = ((double)f.o[a] - s.org[a]) * s.gs;
+    const double dgd = (double)f.d[a] * s.gs;
+    rel[a] = (float)((ogd - (double)h.lo[a]) + (double)h.t_in * dgd);
+    stp[a] = (float)(dt * dgd / S);
+  }
+  sc = 2.0f / (float)h.size;
+}
+
+// Front-to-back walk over the voxels a ray hits: calls visit(hit) for each, in increasing t_in,
+// until visit returns false.  Each voxel is reported exactly once with the rule's interval.
+//
+// The walk keeps one running parameter t.  At root level it keeps, per axis, the root-cell index
+// whose slab [crossing of its entry plane, crossing of its exit plane) contains t; an empty root
+// cell whose Chebyshev distance to occupied cells is d > 1 lets the walk jump to where the ray
+// leaves the empty cube of radius d - 1 around it (every cell the ray meets before that is in the
+// cube).  Inside an occupied root cell, each pass of the leaf loop (1) descends from the current
+// node to the leaf holding t, choosing at every level the octant whose half-open slabs contain t
+// (t against the mid-plane crossings) and pushing internal nodes on a per-lane stack (LDS,
+// stk[depth * stride]); (2) reports the leaf if it holds a voxel; (3) moves t to the leaf's exit
+// crossing and pops every node that t has left.  All lanes of a wave therefore report at most one
+// voxel per pass, at the same point of the loop, which keeps shading convergent.
+//
+// Every bound is a crossing the rule itself computes.  The leaf found contains t, so its t_in
+// (the largest of its entry crossings and t_near) is exactly t, and its t_out is its exit crossing
+// capped by t_far: neither needs recomputing.  t strictly increases, and a step budget bounds the
+// walk regardless.
+template <typename Visit>
+__device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* stk, int stride, Visit&& visit) {
+  if (!f.valid) return;
+  const int K = s.K;
+  float t, t_exit;
+  {
+    const int32_t glo[3] = {0, 0, 0};
+    const int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
+    if (!box_interval(f, glo, ghi, t, t_exit)) return;
+    if (!(t < t_exit)) return;
+  }
+  RootAxis ax, ay, az;
+  root_axis_init<0>(f, s, t, ax);
+  root_axis_init<1>(f, s, t, ay);
+  root_axis_init<2>(f, s, t, az);
+  const int32_t N0 = 1 << K;
+  int budget = 1 << 22;
+  Hit h;
+  while (budget-- > 0) {
+    const float cell_exit = fminf(fminf(ax.nxt, ay.nxt), fminf(az.nxt, t_exit));
+    const int64_t lin = ((int64_t)az.k * s.dims[1] + ay.k) * s.dims[0] + ax.k;
+    const int32_t code = s.root[lin];
+    float t_next = cell_exit;
+    if (code >= 0) {
+      // octree of this root cell
+      int depth = 0;
+      int32_t size = N0;
+      int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
+      stk[0] = code;
+      const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
+      int4 c0 = np[0], c1 = np[1];
+      float tc = t;
+      while (tc < cell_exit && budget-- > 0) {
+        // (1) descend to the leaf holding tc
+        int32_t clo[3], half, child;
+        for (;;) {
+          half = size >> 1;
+          int c8 = 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int32_t mid = lo[a] + half;
+            bool upper;
+            if (f.par & (1 << a)) {
+              upper = f.og[a] >= (float)mid;
+            } else {
+              const bool past = plane_t((float)mid, f.og[a], f.inv[a]) <= tc;
+              upper = (f.inv[a] > 0.0f) ? past : !past;
+            }
+            clo[a] = upper ? mid : lo[a];
+            c8 |= upper ? (1 << a) : 0;
+          }
+          child = pick8(c0, c1, c8);
+          // internal children exist only above the finest level; deeper would be malformed: empty
+          if (child < 0 || depth + 1 >= K) break;
+          ++depth;
+          stk[depth * stride] = child;
+          size = half;
+          lo[0] = clo[0];
+          lo[1] = clo[1];
+          lo[2] = clo[2];
+          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)child * 8);
+          c0 = np[0];
+          c1 = np[1];
+        }
+        // (2) the leaf [clo, clo + half): report a voxel
+        const float to = box_exit(f, clo, half);
+        if (is_leaf_code(child)) {
+          h.voxel = leaf_voxel(child);
+          h.lo[0] = clo[0];
+          h.lo[1] = clo[1];
+          h.lo[2] = clo[2];
+          h.size = half;
+          h.t_in = tc;
+          h.t_out = to;
+          if (!visit(h)) return;
+        }
+        // (3) advance and leave every node that no longer holds tc
+        if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
+        tc = to;
+        if (!(tc < cell_exit)) break;
+        bool popped = false;
+        while (depth > 0 && !(tc < box_exit(f, lo, size))) {
+          --depth;
+          size <<= 1;
+          lo[0] &= ~(size - 1);
+          lo[1] &= ~(size - 1);
+          lo[2] &= ~(size - 1);
+          popped = true;
+        }
+        if (popped) {
+          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)stk[depth * stride] * 8);
+          c0 = np[0];
+          c1 = np[1];
+        }
+      }
+    } else if (is_leaf_code(code)) {
+      // a level-0 voxel fills the root cell: it holds t, so its interval is [t, cell_exit]
+      h.voxel = leaf_voxel(code);
+      h.lo[0] = ax.k << K;
+      h.lo[1] = ay.k << K;
+      h.lo[2] = az.k << K;
+      h.size = N0;
+      h.t_in = t;
+      h.t_out = cell_exit;
+      if (!visit(h)) return;
+    } else if (s.skip != nullptr) {
+      const int d = s.skip[lin];
+      if (d > 1)  // leave the empty cube of radius d - 1 around this cell
+        t_next = fminf(fminf(cube_exit<0>(f, s, ax, d), cube_exit<1>(f, s, ay, d)),
+                       fminf(cube_exit<2>(f, s, az, d), t_exit));
+    }
+    if (!(t_next < t_exit)) return;
+    t = t_next;
+    if (!root_axis_advance<0>(f, s, t, ax) || !root_axis_advance<1>(f, s, t, ay) ||
+        !root_axis_advance<2>(f, s, t, az))
+      return;
+  }
+}
+
 
 // ----------------------------------------------------------------------------- sensors
 __device__ inline void rotate_rodrigues(const float w[3], float dt, float v[3]) {

@@ -14,12 +14,12 @@ namespace salf {
 salf_status set_error(salf_status code, const char* fmt, ...);
 salf_status check_hip(hipError_t e, const char* what);
 
-// ---- scene workspace layout: [root grid][nodes][hash keys][hash values][counters]
+// ---- scene workspace layout: [root grid][skip grid][nodes][hash keys][hash values][2 temp grids][counters]
 struct SceneLayout {
   int64_t n_root;        // root cells
   int64_t node_cap;      // internal nodes the workspace can hold
   int64_t hash_cap;      // hash slots (power of two)
-  size_t root_off, nodes_off, hkeys_off, hvals_off, counters_off, total;
+  size_t root_off, skip_off, nodes_off, hkeys_off, hvals_off, tmp_off, counters_off, total;
 };
 bool scene_layout(const salf_scene_desc& d, int64_t n_voxels, SceneLayout* out);
 

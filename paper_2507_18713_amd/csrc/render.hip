@@ -21,9 +21,10 @@ struct Accum {
 // Shade one voxel segment [ti, to] and composite it into acc.  Returns false once the ray has
 // become opaque enough to stop (T < t_min after the voxel).
 template <int FIELD, bool RGB, bool INT>
-__device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], int32_t v,
-                                            const int32_t lo[3], int32_t size, float ti, float to, int S, float t_min,
-                                            Accum& acc) {
+__device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
+                                            int S, float t_min, Accum& acc) {
+  const int32_t v = h.voxel;
+  const float ti = h.t_in;
   // corner parameters of the voxel (coalescing across lanes comes from coherent rays)
   float g[8], c[3][8], it[8];
   {
@@ -64,16 +65,8 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
     for (int ch = 0; ch < 3; ++ch) shc[ch] = c[ch][3] * sh[0] + c[ch][4] * sh[1] + c[ch][5] * sh[2] + c[ch][6] * sh[3];
   }
 
-  // sample positions relative to the voxel, formed in FP64 and kept small in FP32
-  const double dt = (double)to - (double)ti;
-  const float delta = (float)(dt / S);  // length of one piece
-  float rel[3], stp[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    rel[a] = (float)((f.ogd[a] - (double)lo[a]) + (double)ti * f.dgd[a]);
-    stp[a] = (float)(dt * f.dgd[a] / S);
-  }
-  const float sc = 2.0f / (float)size;
+  float rel[3], stp[3], delta, sc;
+  segment_frame(s, f, h, S, rel, stp, delta, sc);
 
   for (int k = 0; k < S; ++k) {
     const float fk = (float)k + 0.5f;
@@ -172,8 +165,9 @@ __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
   acc.n = 0;
   const int S = p.S;
   const float t_min = p.t_min;
-  traverse(p.scene, f, [&](int32_t v, const int32_t lo[3], int32_t size, float ti, float to) -> bool {
-    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, v, lo, size, ti, to, S, t_min, acc);
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  traverse(p.scene, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, t_min, acc);
   });
   const salf_outputs& out = p.out;
   if (out.rgb) {
@@ -200,11 +194,12 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays 
   const RayFrame f = make_frame(s, o, d, r.t_near, r.t_far);
   int32_t n = 0;
   const int64_t base = ray * (int64_t)max_hits;
-  traverse(s, f, [&](int32_t v, const int32_t*, int32_t, float ti, float to) -> bool {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     if (n < max_hits) {
-      ids[base + n] = v;
-      t_in[base + n] = ti;
-      t_out[base + n] = to;
+      ids[base + n] = h.voxel;
+      t_in[base + n] = h.t_in;
+      t_out[base + n] = h.t_out;
     }
     ++n;
     return true;
@@ -266,7 +261,10 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const int S = p.S;
   float T = 1.0f, PC[3] = {0.0f, 0.0f, 0.0f}, PD = 0.0f, PI = 0.0f;
   int32_t count = 0;
-  traverse(s, f, [&](int32_t v, const int32_t lo[3], int32_t size, float ti, float to) -> bool {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+    const int32_t v = h.voxel;
+    const float ti = h.t_in;
     float zg[8], sp[8], zr[3][8], cr[3][8], zi[8], ci[8];
     {
       const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
@@ -293,15 +291,8 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) ci[i] = sigmoid_f(zi[i]);
     }
-    const double dt = (double)to - (double)ti;
-    const float delta = (float)(dt / S);
-    float rel[3], stp[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      rel[a] = (float)((f.ogd[a] - (double)lo[a]) + (double)ti * f.dgd[a]);
-      stp[a] = (float)(dt * f.dgd[a] / S);
-    }
-    const float sc = 2.0f / (float)size;
+    float rel[3], stp[3], delta, sc;
+    segment_frame(s, f, h, S, rel, stp, delta, sc);
     float ag[8], ar[3][8], ai[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {

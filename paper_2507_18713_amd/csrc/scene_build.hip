@@ -158,6 +158,33 @@ __global__ void link_kernel(BuildArgs a) {
   }
 }
 
+// Chebyshev distance from every root cell to the nearest occupied one (0 = occupied), capped at
+// kSkipCap, by three separable passes: along x, then y, then z, each taking
+// d(c) = min over |j| <= cap of max(|j|, d_prev(c + j e_axis)).
+constexpr int kSkipCap = 24;
+
+__global__ void skip_pass(const int32_t* root, const uint8_t* in, uint8_t* out, int axis, int32_t dx, int32_t dy,
+                          int32_t dz) {
+  const int64_t n = (int64_t)dx * dy * dz;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t x = (int32_t)(i % dx), y = (int32_t)((i / dx) % dy), z = (int32_t)(i / ((int64_t)dx * dy));
+  const int32_t c = axis == 0 ? x : (axis == 1 ? y : z);
+  const int32_t D = axis == 0 ? dx : (axis == 1 ? dy : dz);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? dx : (int64_t)dx * dy);
+  int best = kSkipCap + 1;
+  for (int j = -kSkipCap; j <= kSkipCap; ++j) {
+    const int32_t q = c + j;
+    if (q < 0 || q >= D) continue;
+    const int64_t qi = i + (int64_t)j * stride;
+    const int prev = (axis == 0) ? (root[qi] != kEmpty ? 0 : kSkipCap + 1) : (int)in[qi];
+    const int aj = j < 0 ? -j : j;
+    const int v = prev > aj ? prev : aj;
+    best = v < best ? v : best;
+  }
+  out[i] = (uint8_t)best;
+}
+
 __global__ void count_roots(const int32_t* root, int64_t n, BuildCounters* c) {
   int32_t mine = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -194,12 +221,16 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   L->hash_cap = hcap;
   L->root_off = off;
   off = up(off + (size_t)n_root * 4);
+  L->skip_off = off;
+  off = up(off + (size_t)n_root);
   L->nodes_off = off;
   off = up(off + (size_t)node_cap * 32);
   L->hkeys_off = off;
   off = up(off + (size_t)hcap * 8);
   L->hvals_off = off;
   off = up(off + (size_t)hcap * 4);
+  L->tmp_off = off;
+  off = up(off + (size_t)n_root * 2);
   L->counters_off = off;
   off = up(off + sizeof(BuildCounters));
   L->total = off;
@@ -229,6 +260,15 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   if (n > 0) insert_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
   number_kernel<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
   if (n > 0) link_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
+  {
+    uint8_t* skip = (uint8_t*)(base + L.skip_off);
+    uint8_t* t0 = (uint8_t*)(base + L.tmp_off);
+    uint8_t* t1 = t0 + L.n_root;
+    const unsigned nb = blocks_for(L.n_root, T);
+    skip_pass<<<nb, T, 0, stream>>>(a.root, nullptr, t0, 0, a.dims[0], a.dims[1], a.dims[2]);
+    skip_pass<<<nb, T, 0, stream>>>(a.root, t0, t1, 1, a.dims[0], a.dims[1], a.dims[2]);
+    skip_pass<<<nb, T, 0, stream>>>(a.root, t1, skip, 2, a.dims[0], a.dims[1], a.dims[2]);
+  }
   count_roots<<<blocks_for(L.n_root, T) > 1024 ? 1024 : blocks_for(L.n_root, T), T, 0, stream>>>(a.root, L.n_root,
                                                                                                   a.cnt);
   return hipGetLastError();
