@@ -122,8 +122,15 @@ typedef struct {
   int32_t root_dims[3];  /* root cells per axis, >= 1                                                */
   int32_t max_level;     /* K in [0, SALF_MAX_LEVEL]                                                 */
   int32_t field;         /* SALF_FIELD_CORNER or SALF_FIELD_PAPER                                    */
-  int32_t reserved;      /* must be 0                                                                */
+  int32_t flags;         /* 0 or SALF_SCENE_PREACTIVATE                                              */
 } salf_scene_desc;
+
+/* Corner field only: the build also stores activated corner values (softplus of the density
+ * logits, sigmoid of the colour and intensity logits) in the workspace, and forward renders read
+ * those instead of activating per hit.  The borrowed logits stay the scene's parameters (the
+ * backward reads them); after updating them in place, call salf_scene_refresh before rendering.
+ * The workspace grows by 4 B per stored corner value. */
+#define SALF_SCENE_PREACTIVATE 1
 
 typedef struct {
   int64_t n_voxels;
@@ -156,6 +163,10 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
                               const int32_t* d_voxels, const float* d_geo, const float* d_rgb,
                               const float* d_int, void* d_workspace, size_t ws_bytes, void* stream,
                               int32_t* scene_id);
+
+/* Recompute a SALF_SCENE_PREACTIVATE scene's activated corner values from its borrowed logits
+ * (asynchronous on `stream`).  A no-op for other scenes.  Errors: NOT_FOUND, DEVICE. */
+salf_status salf_scene_refresh(salf_context* ctx, int32_t scene_id, void* stream);
 
 /* Statistics of a built scene.  Errors: NOT_FOUND. */
 salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out);

@@ -15,12 +15,13 @@ SALF_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUDGET",
                 -6: "BUSY", -7: "UNSUPPORTED"}
 FIELD_CORNER, FIELD_PAPER = 0, 1
+SCENE_PREACTIVATE = 1
 PINHOLE, FISHEYE_EQUIDISTANT, LIDAR_SPINNING = 0, 1, 2
 
 
 class SceneDesc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("root_size", C.c_double), ("root_dims", C.c_int32 * 3),
-                ("max_level", C.c_int32), ("field", C.c_int32), ("reserved", C.c_int32)]
+                ("max_level", C.c_int32), ("field", C.c_int32), ("flags", C.c_int32)]
 
 
 class SceneStats(C.Structure):
@@ -67,6 +68,7 @@ SIGNATURES = {
     "salf_scene_create": (C.c_int32, [C.c_void_p, C.POINTER(SceneDesc), C.c_int64, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.POINTER(C.c_int32)]),
+    "salf_scene_refresh": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "salf_scene_get_stats": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SceneStats)]),
     "salf_scene_destroy": (C.c_int32, [C.c_void_p, C.c_int32]),
     "salf_sensor_ray_count": (C.c_int32, [C.POINTER(Sensor), C.POINTER(C.c_int64)]),
@@ -95,7 +97,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2507_18713_amd.build`")
+            raise ImportError(f"{LIB_PATH} is not built; run `python paper_2507_18713_amd/build.py`")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -74,7 +74,9 @@ class Scene:
 
     def __init__(self, voxels: torch.Tensor, geo: torch.Tensor, rgb: Optional[torch.Tensor],
                  intensity: Optional[torch.Tensor], origin, root_size: float, root_dims, max_level: int,
-                 field: str = "corner"):
+                 field: str = "corner", preactivate: bool = False):
+        """preactivate (corner field): store activated corner values at build time; forward
+        renders read them (call refresh() after updating the parameters in place)."""
         dev = geo.device
         self.ctx = Context.get(dev)
         n = int(voxels.shape[0])
@@ -90,7 +92,7 @@ class Scene:
         d.root_dims[:] = [int(x) for x in root_dims]
         d.max_level = int(max_level)
         d.field = FIELDS[field]
-        d.reserved = 0
+        d.flags = _lib.SCENE_PREACTIVATE if preactivate else 0
         nbytes = C.c_size_t()
         call("salf_scene_workspace_size", C.byref(d), n, C.byref(nbytes))
         self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
@@ -108,12 +110,17 @@ class Scene:
         self.device = dev
         self.n = n
         self.field = field
+        self.preactivate = preactivate
         self.geo, self.rgb, self.intensity = geo, rgb, intensity
         self._voxels = voxels
 
+    def refresh(self):
+        """Re-derive the stored activated corner values from the parameters (pre-activated scenes)."""
+        call("salf_scene_refresh", self.ctx.handle, self.id, _stream(self.device))
+
     @classmethod
     def from_data(cls, data, device="cuda", field: str = "corner", rgb: bool = True, intensity: bool = True,
-                  requires_grad: bool = False) -> "Scene":
+                  requires_grad: bool = False, preactivate: bool = False) -> "Scene":
         """Upload a scene given as numpy arrays (attributes origin, root_size, root_dims, max_level,
         voxels [N,4] int32, z_geo [N,8], z_rgb [N,3,8], z_int [N,8] or None)."""
         dev = torch.device(device)
@@ -129,7 +136,8 @@ class Scene:
             for t in (geo, col, ity):
                 if t is not None:
                     t.requires_grad_(True)
-        return cls(vox, geo, col, ity, data.origin, data.root_size, data.root_dims, data.max_level, field)
+        return cls(vox, geo, col, ity, data.origin, data.root_size, data.root_dims, data.max_level, field,
+                   preactivate)
 
     def stats(self) -> dict:
         s = _lib.SceneStats()

@@ -79,7 +79,9 @@ salf_status validate_desc(const salf_scene_desc* d) {
   }
   if (d->field != SALF_FIELD_CORNER && d->field != SALF_FIELD_PAPER)
     return set_error(SALF_ERR_INVALID_ARG, "unknown field mode %d", d->field);
-  if (d->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
+  if (d->flags & ~SALF_SCENE_PREACTIVATE) return set_error(SALF_ERR_INVALID_ARG, "unknown scene flags %d", d->flags);
+  if ((d->flags & SALF_SCENE_PREACTIVATE) && d->field != SALF_FIELD_CORNER)
+    return set_error(SALF_ERR_INVALID_ARG, "SALF_SCENE_PREACTIVATE applies to the corner field only");
   return SALF_OK;
 }
 
@@ -261,6 +263,16 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.root = (const int32_t*)((char*)d_workspace + L.root_off);
   v.nodes = (const int32_t*)((char*)d_workspace + L.nodes_off);
   v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
+  v.act_geo = v.act_rgb = v.act_int = nullptr;
+  if (desc->flags & SALF_SCENE_PREACTIVATE) {
+    v.act_geo = (const float*)((char*)d_workspace + L.act_geo_off);
+    v.act_rgb = d_rgb ? (const float*)((char*)d_workspace + L.act_rgb_off) : nullptr;
+    v.act_int = d_int ? (const float*)((char*)d_workspace + L.act_int_off) : nullptr;
+    if ((st = check_hip(launch_activate(d_geo, d_rgb, d_int, n_voxels, (float*)v.act_geo, (float*)v.act_rgb,
+                                        (float*)v.act_int, s),
+                        "activation launch")))
+      return st;
+  }
   v.geo = d_geo;
   v.rgb = d_rgb;
   v.inten = d_int;
@@ -283,6 +295,18 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   ctx->scenes.push_back(sc);
   *scene_id = (int32_t)(ctx->scenes.size() - 1);
   return SALF_OK;
+}
+
+salf_status salf_scene_refresh(salf_context* ctx, int32_t scene_id, void* stream) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  const SceneView& v = sc->view;
+  if (v.act_geo == nullptr) return SALF_OK;
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_activate(v.geo, v.rgb, v.inten, sc->n, (float*)v.act_geo, (float*)v.act_rgb,
+                                   (float*)v.act_int, (hipStream_t)stream),
+                   "activation launch");
 }
 
 salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out) {

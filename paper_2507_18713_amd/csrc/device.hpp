@@ -16,6 +16,9 @@
 namespace salf {
 
 constexpr int32_t kEmpty = -1;          // empty cell / child
+// Field variants of the render kernels: the two of salf.h plus the corner field read from stored
+// activated corner values.
+constexpr int kFieldCornerActivated = 2;
 __host__ __device__ inline bool is_leaf_code(int32_t c) { return c <= -2; }
 __host__ __device__ inline int32_t leaf_code(int32_t voxel) { return -2 - voxel; }
 __host__ __device__ inline int32_t leaf_voxel(int32_t code) { return -2 - code; }
@@ -29,6 +32,9 @@ struct SceneView {
   const float* inten;    // [N][8] or null
   const uint8_t* skip;   // [Dz][Dy][Dx] Chebyshev distance (in root cells, capped) to the nearest
                          // occupied root cell; 0 = occupied.  Null: no empty-space skipping.
+  const float* act_geo;  // activated corner values (pre-activated corner scenes), same layouts as
+  const float* act_rgb;  // geo / rgb / inten; null otherwise
+  const float* act_int;
   int32_t dims[3];       // root cells per axis
   int32_t K;             // finest level
   float org32[3];        // grid origin, FP32

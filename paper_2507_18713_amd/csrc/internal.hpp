@@ -19,7 +19,9 @@ struct SceneLayout {
   int64_t n_root;        // root cells
   int64_t node_cap;      // internal nodes the workspace can hold
   int64_t hash_cap;      // hash slots (power of two)
-  size_t root_off, skip_off, nodes_off, hkeys_off, hvals_off, tmp_off, counters_off, total;
+  size_t root_off, skip_off, nodes_off, hkeys_off, hvals_off, tmp_off, counters_off;
+  size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
+  size_t total;
 };
 bool scene_layout(const salf_scene_desc& d, int64_t n_voxels, SceneLayout* out);
 
@@ -30,6 +32,10 @@ struct BuildCounters {
   int32_t n_nodes;        // internal nodes allocated
   int32_t n_occupied;     // occupied root cells
 };
+
+// Activated corner values: dst[i] = softplus(src[i]) for density, sigmoid for colour/intensity.
+hipError_t launch_activate(const float* geo, const float* rgb, const float* inten, int64_t n_voxels, float* act_geo,
+                           float* act_rgb, float* act_int, hipStream_t stream);
 
 hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n_voxels, const int32_t* voxels,
                               const SceneLayout& L, void* ws, hipStream_t stream);

@@ -26,14 +26,18 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
   const int32_t v = h.voxel;
   const float ti = h.t_in;
   // corner parameters of the voxel (coalescing across lanes comes from coherent rays)
+  constexpr bool kAct = FIELD == kFieldCornerActivated;
+  const float* geo = kAct ? s.act_geo : s.geo;
+  const float* rgb = kAct ? s.act_rgb : s.rgb;
+  const float* itn = kAct ? s.act_int : s.inten;
   float g[8], c[3][8], it[8];
   {
-    const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
+    const float4* gp = reinterpret_cast<const float4*>(geo + (int64_t)v * 8);
     const float4 g0 = gp[0], g1 = gp[1];
     g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w; g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
   }
   if (RGB) {
-    const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
+    const float4* cp = reinterpret_cast<const float4*>(rgb + (int64_t)v * 24);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       const float4 a = cp[2 * ch], b = cp[2 * ch + 1];
@@ -42,7 +46,7 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
     }
   }
   if (INT) {
-    const float4* ip = reinterpret_cast<const float4*>(s.inten + (int64_t)v * 8);
+    const float4* ip = reinterpret_cast<const float4*>(itn + (int64_t)v * 8);
     const float4 a = ip[0], b = ip[1];
     it[0] = a.x; it[1] = a.y; it[2] = a.z; it[3] = a.w; it[4] = b.x; it[5] = b.y; it[6] = b.z; it[7] = b.w;
   }
@@ -60,7 +64,7 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
 #pragma unroll
       for (int i = 0; i < 8; ++i) it[i] = sigmoid_f(it[i]);
     }
-  } else if (RGB) {
+  } else if (FIELD == SALF_FIELD_PAPER && RGB) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) shc[ch] = c[ch][3] * sh[0] + c[ch][4] * sh[1] + c[ch][5] * sh[2] + c[ch][6] * sh[3];
   }
@@ -74,7 +78,7 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
 #pragma unroll
     for (int a = 0; a < 3; ++a) x[a] = fminf(fmaxf((rel[a] + fk * stp[a]) * sc - 1.0f, -1.0f), 1.0f);
     float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-    if (FIELD == SALF_FIELD_CORNER) {
+    if (FIELD != SALF_FIELD_PAPER) {
       float w[8];
       corner_weights(x, w);
       sigma = 0.0f;
@@ -394,6 +398,7 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
   if (field == SALF_FIELD_PAPER) return launch_field<SALF_FIELD_PAPER>(p, blocks, stream);
+  if (p.scene.act_geo != nullptr) return launch_field<kFieldCornerActivated>(p, blocks, stream);
   return launch_field<SALF_FIELD_CORNER>(p, blocks, stream);
 }
 

@@ -233,8 +233,36 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   off = up(off + (size_t)n_root * 2);
   L->counters_off = off;
   off = up(off + sizeof(BuildCounters));
+  L->act_geo_off = L->act_rgb_off = L->act_int_off = 0;
+  if (d.flags & SALF_SCENE_PREACTIVATE) {
+    L->act_geo_off = off;
+    off = up(off + (size_t)n * 8 * 4);
+    L->act_rgb_off = off;
+    off = up(off + (size_t)n * 24 * 4);
+    L->act_int_off = off;
+    off = up(off + (size_t)n * 8 * 4);
+  }
   L->total = off;
   return true;
+}
+
+namespace {
+// Corner activations for pre-activated scenes (the same functions the render kernels apply).
+__global__ void activate_kernel(const float* src, float* dst, int64_t n, int softplus) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = softplus ? softplus_f(src[i]) : sigmoid_f(src[i]);
+}
+}  // namespace
+
+hipError_t launch_activate(const float* geo, const float* rgb, const float* inten, int64_t n, float* act_geo,
+                           float* act_rgb, float* act_int, hipStream_t stream) {
+  const int T = 256;
+  auto grid = [](int64_t m) { return (unsigned)((m + 255) / 256 > 8192 ? 8192 : (m + 255) / 256); };
+  if (n <= 0) return hipSuccess;
+  activate_kernel<<<grid(n * 8), T, 0, stream>>>(geo, act_geo, n * 8, 1);
+  if (rgb) activate_kernel<<<grid(n * 24), T, 0, stream>>>(rgb, act_rgb, n * 24, 0);
+  if (inten) activate_kernel<<<grid(n * 8), T, 0, stream>>>(inten, act_int, n * 8, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t* voxels, const SceneLayout& L,

@@ -42,7 +42,7 @@ def test_struct_layout_matches_the_header(L):
 #include <stddef.h>
 #include "salf.h"
 int main(void) {
-  printf("SceneDesc %zu %zu %zu\n", sizeof(salf_scene_desc), offsetof(salf_scene_desc, root_dims), offsetof(salf_scene_desc, reserved));
+  printf("SceneDesc %zu %zu %zu\n", sizeof(salf_scene_desc), offsetof(salf_scene_desc, root_dims), offsetof(salf_scene_desc, flags));
   printf("SceneStats %zu %zu\n", sizeof(salf_scene_stats), offsetof(salf_scene_stats, workspace_bytes));
   printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
   printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
@@ -61,7 +61,7 @@ int main(void) {
     got = {ln.split()[0]: [int(x) for x in ln.split()[1:]] for ln in out if ln.strip()}
     S = L
     want = {
-        "SceneDesc": [C.sizeof(S.SceneDesc), S.SceneDesc.root_dims.offset, S.SceneDesc.reserved.offset],
+        "SceneDesc": [C.sizeof(S.SceneDesc), S.SceneDesc.root_dims.offset, S.SceneDesc.flags.offset],
         "SceneStats": [C.sizeof(S.SceneStats), S.SceneStats.workspace_bytes.offset],
         "Sensor": [C.sizeof(S.Sensor), S.Sensor.R0.offset, S.Sensor.t_far.offset],
         "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
@@ -79,7 +79,7 @@ def _desc(L, dims=(4, 4, 4), K=2, s0=1.0, field=0):
     d.root_dims[:] = list(dims)
     d.max_level = K
     d.field = field
-    d.reserved = 0
+    d.flags = 0
     return d
 
 

@@ -27,7 +27,9 @@ def _close(g, ref, rel=1e-3, absr=1e-5):
     scale = np.max(np.abs(ref))
     assert scale > 0
     err = np.abs(g - ref) - (rel * np.abs(ref) + absr * scale)
-    assert np.max(err) <= 0, float(np.max(np.abs(g - ref)))
+    worst = np.argsort(-err.ravel())[:5]
+    detail = [(int(i), float(g.ravel()[i]), float(ref.ravel()[i])) for i in worst]
+    assert np.max(err) <= 0, detail
 
 
 @pytest.mark.parametrize("which", ["tiny", "adaptive"])
@@ -99,9 +101,13 @@ def test_gradient_matches_finite_differences_on_driving_scene(salf):
     dr = dr.cpu().numpy()
     # voxels by the number of rays that cross them
     cnt_c, ids_c, _, _ = salf.trace_hits(scene, Oc, Dc, 512)
-    cnt_l, ids_l, _, _ = salf.trace_hits(scene, Ol, Dl, 512)
+    cnt_l, ids_l, tin_l, _ = salf.trace_hits(scene, Ol, Dl, 512)
     hc = np.bincount(np.maximum(ids_c.cpu().numpy().ravel(), 0), minlength=data.n)
-    hl = np.bincount(np.maximum(ids_l.cpu().numpy().ravel(), 0), minlength=data.n)
+    # LiDAR voxels within 8 m: the float32 depth rounding (about 5e-7 m there) stays far below the
+    # central difference of the loss
+    il = ids_l.cpu().numpy().ravel()
+    near = (il >= 0) & (tin_l.cpu().numpy().ravel() < 8.0)
+    hl = np.bincount(il[near], minlength=data.n)
     hc[0] = hl[0] = 0
     dense_c = np.nonzero(hc >= 16)[0]
     dense_l = np.nonzero((hl >= 8) & (hc == 0))[0]

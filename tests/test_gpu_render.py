@@ -288,3 +288,31 @@ def test_fused_sensor_render_equals_explicit_rays(salf):
             a, b = fused[k], expl[k]
             assert torch.equal(a[valid], b[valid]), k
         assert torch.all(fused["opacity"][~valid] == 0)
+
+
+def test_preactivated_scene_matches_oracle_and_refreshes(salf):
+    data = synth.random_scene(63, root_dims=(6, 5, 4), max_level=2)
+    ps = oracle.prepare(data)
+    raw = salf.Scene.from_data(data, device=dev())
+    pre = salf.Scene.from_data(data, device=dev(), preactivate=True)
+    o, d = synth.random_rays(64, 600, data.origin, data.origin + data.root_dims * data.root_size)
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    a = salf.render(raw, o=to_dev(o), d=to_dev(d), outputs=outs)
+    b = salf.render(pre, o=to_dev(o), d=to_dev(d), outputs=outs)
+    check_outputs(b, oracle.render_rays(ps, o, d, RenderOpts()))
+    for k in outs:
+        assert torch.allclose(a[k].float(), b[k].float(), atol=1e-6, rtol=0), k
+    # in-place parameter update: stale until refresh, then equal to a fresh raw render
+    with torch.no_grad():
+        pre.geo.add_(0.5)
+        pre.rgb.mul_(-1.0)
+    stale = salf.render(pre, o=to_dev(o), d=to_dev(d), outputs=outs)
+    assert torch.equal(stale["rgb"], b["rgb"])
+    pre.refresh()
+    fresh = salf.render(pre, o=to_dev(o), d=to_dev(d), outputs=outs)
+    data2 = data.permuted(np.arange(data.n))
+    data2.z_geo = data.z_geo + np.float32(0.5)
+    data2.z_rgb = -data.z_rgb
+    check_outputs(fresh, oracle.render_rays(oracle.prepare(data2), o, d, RenderOpts()))
+    with pytest.raises(salf.SalfError, match="corner field only"):
+        salf.Scene.from_data(data, device=dev(), field="paper", preactivate=True)
