@@ -100,6 +100,134 @@ def cpu_baseline(n_cam=480, n_lid=32, seed=5):
                       f"against all voxels of the driving scene; {cpu_s:.1f} CPU-s in {wall:.1f} s wall"}
 
 
+# ------------------------------------------------------------------ serving (vehicle sensor rigs)
+def vehicle_tick(rng, scene_index):
+    """One vehicle tick: 6 pinholes 1920x1080 (HFOV 70, yaw 0, +-60, +-120, 180) and 2 equidistant
+    fisheyes 1280x960 (190 deg, yaw +-90), each with a 30 us/row rolling shutter, and 2 spinning
+    LiDARs (roof at 1.9 m, front bumper at 0.7 m), at a random pose on the road moving at 10 m/s."""
+    import numpy as np
+
+    import synth
+    x = rng.uniform(-80.0, 80.0)
+    lane = rng.choice([-1.75, 1.75])
+    heading = 0.0 if rng.random() < 0.5 else 180.0
+    c, s = math.cos(math.radians(heading)), math.sin(math.radians(heading))
+    v = (10.0 * c, 10.0 * s, 0.0)
+    frames = []
+    for yaw in (0.0, 60.0, -60.0, 120.0, -120.0, 180.0):
+        frames.append(("camera", synth.pinhole(1920, 1080, 70.0, synth.yaw_pitch_camera(heading + yaw, -3.0),
+                                               (x, lane, 1.6), dt_line=30e-6, v=v)))
+    for yaw in (90.0, -90.0):
+        frames.append(("fisheye", synth.fisheye_equidistant(1280, 960, 190.0, synth.yaw_pitch_camera(heading + yaw, 0.0),
+                                                            (x, lane, 1.5), dt_line=30e-6, v=v)))
+    for z, dx in ((1.9, 0.0), (0.7, 2.0)):
+        frames.append(("lidar", synth.lidar_spinning(64, 2048, -25.0, 15.0, synth.yaw_lidar(heading),
+                                                     (x + dx * c, lane + dx * s, z), 0.1, v=v)))
+    return [(kind, sen, scene_index) for kind, sen in frames]
+
+
+OUTS = {"camera": ("rgb", "depth", "opacity"), "fisheye": ("rgb", "depth", "opacity"),
+        "lidar": ("depth", "intensity", "opacity")}
+FISHEYE_VALID = 1101128  # rays inside the 190 deg circle of a 1280x960 equidistant fisheye
+
+
+def frame_rays(kind, sen):
+    return FISHEYE_VALID if kind == "fisheye" else sen["width"] * sen["height"]
+
+
+def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1.0):
+    """Poisson arrivals of vehicle ticks over 4 resident scenes: plain FIFO rendering (one frame at
+    a time on one stream) against the continuous-batching server, at 0.5x, 0.9x and 1.5x the plain
+    capacity and in a closed loop (all ticks queued at once).  Latency = arrival to completion on
+    the host monotonic clock, per frame."""
+    import numpy as np
+
+    import synth
+    scenes = [salf.Scene.from_data(synth.config1_variant(s), device=dev, preactivate=True) for s in (11, 12, 13, 14)]
+    rng = np.random.default_rng(seed)
+    ticks = [vehicle_tick(rng, int(rng.integers(0, 4))) for _ in range(n_ticks + warm_ticks)]
+    opts = dict(samples=4, t_min=1e-6)
+
+    def plain_run(arrivals):
+        # a single worker renders queued frames in arrival order, one at a time
+        done, order, q = [], [], []
+        t0 = time.monotonic()
+        i = 0
+        frames = [(arrivals[k], f) for k, tk in enumerate(ticks) for f in tk]
+        while len(done) < len(frames):
+            now = time.monotonic() - t0
+            while i < len(frames) and frames[i][0] <= now:
+                q.append(frames[i])
+                i += 1
+            if not q:
+                time.sleep(max(0.0, frames[i][0] - now))
+                continue
+            arr, (kind, sen, si) = q.pop(0)
+            salf.render(scenes[si], sensor=sen, outputs=OUTS[kind], **opts)
+            torch.cuda.synchronize()
+            done.append((kind, arr, time.monotonic() - t0, frame_rays(kind, sen)))
+        return done
+
+    def served_run(arrivals, srv):
+        frames = [(arrivals[k], f) for k, tk in enumerate(ticks) for f in tk]
+        t0 = time.monotonic()
+        pending, done = {}, []
+        i = 0
+        while len(done) < len(frames):
+            now = time.monotonic() - t0
+            while i < len(frames) and frames[i][0] <= now:
+                arr, (kind, sen, si) = frames[i]
+                pending[srv.submit(scenes[si], sen, outputs=OUTS[kind], **opts)] = (kind, arr, frame_rays(kind, sen))
+                i += 1
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is None:
+                    continue
+                kind, arr, n = pending.pop(tk)
+                done.append((kind, arr, r[2] - t0, n))
+                srv.release(tk)
+            if pending or i < len(frames):
+                time.sleep(0.0002)
+        return done
+
+    def summarize(done, warm_frames):
+        done = sorted(done, key=lambda d: d[1])[warm_frames:]
+        lat = np.array([d[2] - d[1] for d in done]) * 1e3
+        span = max(d[2] for d in done) - min(d[1] for d in done)
+        rays = sum(d[3] for d in done)
+        per = {}
+        for kind in ("camera", "fisheye", "lidar"):
+            l = np.array([d[2] - d[1] for d in done if d[0] == kind]) * 1e3
+            per[kind] = {"p50_ms": round(float(np.percentile(l, 50)), 2), "p99_ms": round(float(np.percentile(l, 99)), 2)}
+        return {"mrays_s": round(rays / span / 1e6, 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "by_sensor": per}
+
+    warm_frames = warm_ticks * 10
+    # plain capacity: closed loop (every tick queued at t = 0)
+    closed = [0.0] * len(ticks)
+    plain_closed = summarize(plain_run(closed), warm_frames)
+    rays_per_tick = sum(frame_rays(k, s) for k, s, _ in ticks[0])
+    lam_p = plain_closed["mrays_s"] * 1e6 / rays_per_tick      # ticks per second the plain path sustains
+    pool = int(pool_gib * (1 << 30))
+    srv = salf.Server(pool_bytes=pool, device=dev, max_batch=32, max_inflight=2)
+    served_closed = summarize(served_run(closed, srv), warm_frames)
+    points = []
+    for load in (0.5, 0.9, 1.5):
+        gaps = rng.exponential(1.0 / (load * lam_p), size=len(ticks))
+        arrivals = list(np.cumsum(gaps) - gaps[0])
+        points.append({"load": load, "ticks_per_s": round(load * lam_p, 2),
+                       "plain": summarize(plain_run(arrivals), warm_frames),
+                       "served": summarize(served_run(arrivals, srv), warm_frames)})
+    st = srv.stats()
+    srv.close()
+    return {"workload": "4 resident driving scenes (seeds 11-14); Poisson vehicle ticks of 6 pinhole 1920x1080 + "
+                        "2 fisheye 1280x960 (190 deg) with 30 us/row rolling shutter + 2 LiDAR 64x2048",
+            "rays_per_tick": rays_per_tick, "ticks": n_ticks, "warmup_ticks": warm_ticks,
+            "pool_bytes": pool, "plain_capacity_ticks_per_s": round(lam_p, 2),
+            "closed_loop": {"plain": plain_closed, "served": served_closed},
+            "poisson": points, "server_launches": st["launches"], "server_pool_peak": st["pool_peak"]}
+
+
 # ------------------------------------------------------------------ GPU
 def main():
     ap = argparse.ArgumentParser()
@@ -107,6 +235,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-ticks", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path runs on a single "
@@ -226,6 +356,9 @@ def main():
         "scene_generate_s": round(t_gen, 2),
         "kernel_source_hash": kernel_source_hash(),
     }
+    if not args.no_serving:
+        rec["serving"] = serving_bench(salf, torch, dev, n_ticks=args.serve_ticks)
+        rec["metric"] = "Mrays/s camera+LiDAR render on 1 GPU; p50/p99 frame latency served vs plain"
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

@@ -289,6 +289,75 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
                                  const salf_outputs* saved, const salf_grads_in* grads, float* d_dgeo,
                                  float* d_drgb, float* d_dint, void* stream);
 
+/* ------------------------------------------------------------------ serving (continuous batching) */
+/* A server renders sensor requests (a scene and a sensor each) for many sensors and resident scenes
+ * with continuous batching: a scheduler thread inside the library admits queued requests in
+ * arrival order as soon as their outputs fit in the caller's HBM pool, and each scheduling cycle
+ * launches one batched kernel over every 8x8 tile of all requests admitted since the previous
+ * launch; waves pull tiles from a counter, so requests of uneven ray counts share the GPU.  Up
+ * to `max_inflight` launches run at once on separate streams, so requests that arrive while
+ * others are on the GPU start without waiting for them.  A request's rays render to the same bits
+ * as with salf_render (the same device function renders a tile in both).  Multi-sensor vehicles
+ * motivate it: the paper notes vehicles carry more than 20 sensors (Sec. 1). */
+
+typedef struct salf_server salf_server;
+
+enum { SALF_OUT_RGB = 1, SALF_OUT_DEPTH = 2, SALF_OUT_OPACITY = 4, SALF_OUT_INTENSITY = 8 };
+
+typedef struct {
+  void* d_pool;          /* device memory the outputs of admitted requests are carved from           */
+  size_t pool_bytes;     /* the HBM budget for outputs of requests in flight                          */
+  void* d_work;          /* device memory for batch descriptors, >= salf_server_work_size() bytes    */
+  size_t work_bytes;
+  int32_t max_batch;     /* requests per launch, 1..256                                               */
+  int32_t max_inflight;  /* launches in flight, 1..4                                                  */
+} salf_server_opts;
+
+typedef struct {
+  int64_t submitted, completed, released, launches;
+  size_t pool_in_use, pool_peak;   /* bytes of the pool held by admitted, unreleased requests       */
+  int32_t queued, inflight;        /* requests waiting for admission / admitted and not yet done   */
+} salf_server_stats;
+
+/* Device bytes of the `d_work` buffer for `opts` (max_batch, max_inflight).  Errors: INVALID_ARG. */
+salf_status salf_server_work_size(const salf_server_opts* opts, size_t* bytes);
+
+/* Pool bytes a request of `sensor` with outputs `outputs` (SALF_OUT_* mask) occupies.
+ * Errors: INVALID_ARG. */
+salf_status salf_server_request_bytes(const salf_sensor* sensor, uint32_t outputs, size_t* bytes);
+
+/* Create a server on ctx's device.  Pool and work buffers are caller memory, 256-byte aligned,
+ * and must outlive the server.  Errors: INVALID_ARG, DEVICE. */
+salf_status salf_server_create(salf_context* ctx, const salf_server_opts* opts, salf_server** out);
+
+/* Queue a render of `sensor` on scene `scene_id` (corner field) with `opts`.  Non-blocking; the
+ * scene must stay alive until the request completes.  *ticket identifies the request.
+ * Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field), BUDGET (its outputs alone exceed the
+ * pool). */
+salf_status salf_server_submit(salf_server* server, int32_t scene_id, const salf_sensor* sensor,
+                               const salf_render_opts* opts, uint32_t outputs, uint64_t* ticket);
+
+/* State of a request: *done = 1 once its outputs are complete in device memory; then `out` (if
+ * not NULL) receives device pointers into the pool (rgb [n,3], depth/opacity/intensity [n] as
+ * requested; t_end and n_hits NULL).  t_submit / t_done: CLOCK_MONOTONIC seconds at submission
+ * and at the moment the scheduler saw the launch finish (t_done = 0 while not done).
+ * Errors: NOT_FOUND. */
+salf_status salf_server_poll(salf_server* server, uint64_t ticket, int32_t* done, salf_outputs* out,
+                             double* t_submit, double* t_done);
+
+/* Block until the request is done or `timeout_s` seconds pass (*done says which).  Errors: NOT_FOUND. */
+salf_status salf_server_wait(salf_server* server, uint64_t ticket, double timeout_s, int32_t* done);
+
+/* Return a done request's pool space (its output pointers become invalid); this may admit waiting
+ * requests.  Errors: NOT_FOUND, BUSY (not done yet). */
+salf_status salf_server_release(salf_server* server, uint64_t ticket);
+
+salf_status salf_server_get_stats(salf_server* server, salf_server_stats* out);
+
+/* Finish every queued and running request, stop the scheduler and free the server's host state
+ * (pool and work buffers stay the caller's).  Errors: INVALID_ARG. */
+salf_status salf_server_destroy(salf_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,10 +5,10 @@ The rendering path runs in hand-written HIP kernels behind the C ABI of `libsalf
 Importing it loads the library and fails loudly if it is not built.
 """
 from ._lib import SalfError, lib as _load_lib, LIB_PATH
-from .api import (Context, Scene, RenderFunction, generate_rays, ray_count, render, render_backward,
+from .api import (Context, Scene, RenderFunction, Server, generate_rays, ray_count, render, render_backward,
                   sensor_struct, trace_hits)
 
 _load_lib()
 
-__all__ = ["SalfError", "LIB_PATH", "Context", "Scene", "RenderFunction", "generate_rays", "ray_count", "render",
-           "render_backward", "sensor_struct", "trace_hits"]
+__all__ = ["SalfError", "LIB_PATH", "Context", "Scene", "RenderFunction", "Server", "generate_rays", "ray_count",
+           "render", "render_backward", "sensor_struct", "trace_hits"]

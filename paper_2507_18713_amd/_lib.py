@@ -57,6 +57,17 @@ class GradsIn(C.Structure):
                 ("d_intensity", C.c_void_p)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("d_pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("d_work", C.c_void_p),
+                ("work_bytes", C.c_size_t), ("max_batch", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("released", C.c_int64),
+                ("launches", C.c_int64), ("pool_in_use", C.c_size_t), ("pool_peak", C.c_size_t),
+                ("queued", C.c_int32), ("inflight", C.c_int32)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "salf_abi_version": (C.c_int32, []),
@@ -81,6 +92,17 @@ SIGNATURES = {
     "salf_render_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
                                          C.POINTER(RenderOpts), C.POINTER(Outputs), C.POINTER(GradsIn), C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "salf_server_work_size": (C.c_int32, [C.POINTER(ServerOpts), C.POINTER(C.c_size_t)]),
+    "salf_server_request_bytes": (C.c_int32, [C.POINTER(Sensor), C.c_uint32, C.POINTER(C.c_size_t)]),
+    "salf_server_create": (C.c_int32, [C.c_void_p, C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
+    "salf_server_submit": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(RenderOpts), C.c_uint32,
+                                       C.POINTER(C.c_uint64)]),
+    "salf_server_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(Outputs),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "salf_server_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_double, C.POINTER(C.c_int32)]),
+    "salf_server_release": (C.c_int32, [C.c_void_p, C.c_uint64]),
+    "salf_server_get_stats": (C.c_int32, [C.c_void_p, C.POINTER(ServerStats)]),
+    "salf_server_destroy": (C.c_int32, [C.c_void_p]),
 }
 
 _lib = None

@@ -315,3 +315,93 @@ class RenderFunction(torch.autograd.Function):
                  "intensity": g_int if sc.intensity is not None and g_int is not None and g_int.numel() else None}
         dg, dr, di = render_backward(sc, ctx.saved, grads, sensor=ctx.sensor, o=ctx.o, d=ctx.d, **ctx.opts)
         return dg, dr, di, None, None, None, None, None
+
+
+_OUT_BITS = {"rgb": 1, "depth": 2, "opacity": 4, "intensity": 8}
+
+
+class Server:
+    """Continuous-batching render server (salf_server_*).  Outputs of admitted requests are carved
+    from a device pool of `pool_bytes` (the HBM budget); results are views into that pool, valid
+    until release()."""
+
+    def __init__(self, pool_bytes: int, device="cuda", max_batch: int = 64, max_inflight: int = 2):
+        dev = torch.device(device)
+        self.ctx = Context.get(dev)
+        self.device = dev
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=dev)
+        op = _lib.ServerOpts()
+        op.d_pool = self.pool.data_ptr()
+        op.pool_bytes = int(pool_bytes)
+        op.max_batch = int(max_batch)
+        op.max_inflight = int(max_inflight)
+        nbytes = C.c_size_t()
+        call("salf_server_work_size", C.byref(op), C.byref(nbytes))
+        self.work = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+        op.d_work = self.work.data_ptr()
+        op.work_bytes = int(self.work.numel())
+        torch.cuda.synchronize(dev)
+        h = C.c_void_p()
+        call("salf_server_create", self.ctx.handle, C.byref(op), C.byref(h))
+        self.handle = h
+        self._meta = {}
+
+    @staticmethod
+    def request_bytes(sensor: dict, outputs=("rgb", "depth", "opacity")) -> int:
+        n = C.c_size_t()
+        mask = sum(_OUT_BITS[k] for k in outputs)
+        call("salf_server_request_bytes", C.byref(sensor_struct(sensor)), mask, C.byref(n))
+        return int(n.value)
+
+    def submit(self, scene: Scene, sensor: dict, outputs=("rgb", "depth", "opacity"), samples: int = 4,
+               t_min: float = 1e-6, background=(0.0, 0.0, 0.0)) -> int:
+        t = C.c_uint64()
+        mask = sum(_OUT_BITS[k] for k in outputs)
+        call("salf_server_submit", self.handle, scene.id, C.byref(sensor_struct(sensor)),
+             C.byref(_opts(samples, t_min, background)), mask, C.byref(t))
+        self._meta[int(t.value)] = (tuple(outputs), int(sensor["width"]) * int(sensor["height"]))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """None while running; else (outputs dict of tensors viewing the pool, t_submit, t_done)."""
+        done = C.c_int32()
+        ob = _lib.Outputs()
+        ts, td = C.c_double(), C.c_double()
+        call("salf_server_poll", self.handle, C.c_uint64(ticket), C.byref(done), C.byref(ob), C.byref(ts),
+             C.byref(td))
+        if not done.value:
+            return None
+        outs, n = self._meta[ticket]
+        base = self.pool.data_ptr()
+        res = {}
+        for k in outs:
+            off = getattr(ob, k) - base
+            cnt = n * 3 if k == "rgb" else n
+            v = self.pool.narrow(0, off, cnt * 4).view(torch.float32)
+            res[k] = v.view(n, 3) if k == "rgb" else v
+        return res, ts.value, td.value
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> bool:
+        done = C.c_int32()
+        call("salf_server_wait", self.handle, C.c_uint64(ticket), C.c_double(timeout), C.byref(done))
+        return bool(done.value)
+
+    def release(self, ticket: int):
+        call("salf_server_release", self.handle, C.c_uint64(ticket))
+        self._meta.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        call("salf_server_get_stats", self.handle, C.byref(s))
+        return {k: int(getattr(s, k)) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            call("salf_server_destroy", self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

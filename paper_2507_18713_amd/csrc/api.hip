@@ -28,22 +28,7 @@ salf_status check_hip(hipError_t e, const char* what) {
   return set_error(SALF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-struct Scene {
-  bool live = false;
-  salf_scene_desc desc;
-  int64_t n = 0;
-  SceneLayout layout;
-  SceneView view;
-  BuildCounters counters;
-};
-
 }  // namespace salf
-
-struct salf_context {
-  int device = 0;
-  std::mutex mu;
-  std::vector<salf::Scene> scenes;
-};
 
 using namespace salf;
 
@@ -85,7 +70,9 @@ salf_status validate_desc(const salf_scene_desc* d) {
   return SALF_OK;
 }
 
-salf_status validate_sensor(const salf_sensor* s) {
+}  // namespace
+
+salf_status salf::validate_sensor(const salf_sensor* s) {
   if (!s) return set_error(SALF_ERR_INVALID_ARG, "sensor is NULL");
   if (s->model != SALF_PINHOLE && s->model != SALF_FISHEYE_EQUIDISTANT && s->model != SALF_LIDAR_SPINNING)
     return set_error(SALF_ERR_INVALID_ARG, "unknown sensor model %d", s->model);
@@ -102,6 +89,8 @@ salf_status validate_sensor(const salf_sensor* s) {
   return SALF_OK;
 }
 
+namespace {
+
 salf_status validate_rays(const salf_rays* r) {
   if (!r) return set_error(SALF_ERR_INVALID_ARG, "rays is NULL");
   if (r->n < 0 || r->n > ((int64_t)1 << 31)) return set_error(SALF_ERR_INVALID_ARG, "ray count out of range");
@@ -113,7 +102,9 @@ salf_status validate_rays(const salf_rays* r) {
   return SALF_OK;
 }
 
-salf_status validate_opts(const salf_render_opts* o) {
+}  // namespace
+
+salf_status salf::validate_opts(const salf_render_opts* o) {
   if (!o) return set_error(SALF_ERR_INVALID_ARG, "render opts is NULL");
   if (o->samples_per_voxel < 1 || o->samples_per_voxel > SALF_MAX_SAMPLES)
     return set_error(SALF_ERR_INVALID_ARG, "samples_per_voxel %d outside [1, %d]", o->samples_per_voxel,
@@ -122,6 +113,17 @@ salf_status validate_opts(const salf_render_opts* o) {
   if (o->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
   return SALF_OK;
 }
+
+salf_status salf::scene_snapshot(salf_context* ctx, int32_t id, Scene* out) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (id < 0 || id >= (int32_t)ctx->scenes.size() || !ctx->scenes[id].live)
+    return set_error(SALF_ERR_NOT_FOUND, "no scene with id %d", id);
+  *out = ctx->scenes[id];
+  return SALF_OK;
+}
+
+namespace {
 
 salf_status find_scene(salf_context* ctx, int32_t id, Scene** out) {
   if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
@@ -263,6 +265,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.root = (const int32_t*)((char*)d_workspace + L.root_off);
   v.nodes = (const int32_t*)((char*)d_workspace + L.nodes_off);
   v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
+  v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
   v.act_geo = v.act_rgb = v.act_int = nullptr;
   if (desc->flags & SALF_SCENE_PREACTIVATE) {
     v.act_geo = (const float*)((char*)d_workspace + L.act_geo_off);

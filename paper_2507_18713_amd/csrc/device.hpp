@@ -27,6 +27,8 @@ __host__ __device__ inline int32_t leaf_voxel(int32_t code) { return -2 - code; 
 struct SceneView {
   const int32_t* root;   // [Dz][Dy][Dx] cell codes: kEmpty, node index (>= 0) or leaf code
   const int32_t* nodes;  // [n_nodes][8] child codes
+  const uint2* nbox;     // [n_nodes] bounds of each node's voxels relative to the node's min corner:
+                         // bytes (lo_x, lo_y, lo_z) in .x and (hi_x - 1, hi_y - 1, hi_z - 1) in .y
   const float* geo;      // [N][8]
   const float* rgb;      // [N][3][8] or null
   const float* inten;    // [N][8] or null
@@ -180,6 +182,18 @@ __device__ __forceinline__ float cube_exit(const RayFrame& f, const SceneView& s
   return plane_t((float)(P << s.K), f.og[A], f.inv[A]);
 }
 
+// The rule's interval of the bounds of a node's voxels (packed relative to the node's min corner
+// `lo`); false if the ray misses them.  Every voxel of the node lies inside these bounds, so a
+// voxel's entry crossing is never before b_in.
+__device__ __forceinline__ bool node_bounds(const RayFrame& f, const int32_t lo[3], const uint2 b, float& b_in,
+                                            float& b_out) {
+  const int32_t blo[3] = {lo[0] + (int32_t)(b.x & 255u), lo[1] + (int32_t)((b.x >> 8) & 255u),
+                          lo[2] + (int32_t)((b.x >> 16) & 255u)};
+  const int32_t bhi[3] = {lo[0] + (int32_t)(b.y & 255u) + 1, lo[1] + (int32_t)((b.y >> 8) & 255u) + 1,
+                          lo[2] + (int32_t)((b.y >> 16) & 255u) + 1};
+  return box_interval(f, blo, bhi, b_in, b_out) && b_in < b_out;
+}
+
 // Child code c8 of the 8 held in two int4 registers, by selects (no indexed register access).
 __device__ __forceinline__ int32_t pick8(const int4 a, const int4 b, int c8) {
   const bool z = (c8 & 4) != 0, y = (c8 & 2) != 0, x = (c8 & 1) != 0;
@@ -256,15 +270,19 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
     const int32_t code = s.root[lin];
     float t_next = cell_exit;
     if (code >= 0) {
-      // octree of this root cell
+      // octree of this root cell, entered where the ray meets the bounds of its voxels
       int depth = 0;
       int32_t size = N0;
       int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
       stk[0] = code;
       const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
       int4 c0 = np[0], c1 = np[1];
-      float tc = t;
-      while (tc < cell_exit && budget-- > 0) {
+      float b_in, b_out;
+      const bool meets = node_bounds(f, lo, s.nbox[code], b_in, b_out);
+      float tc = fmaxf(t, b_in);
+      const float cell_end = fminf(cell_exit, b_out);
+      if (!meets) tc = cell_end;
+      while (tc < cell_end && budget-- > 0) {
         // (1) descend to the leaf holding tc
         int32_t clo[3], half, child;
         for (;;) {
@@ -286,15 +304,26 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
           child = pick8(c0, c1, c8);
           // internal children exist only above the finest level; deeper would be malformed: empty
           if (child < 0 || depth + 1 >= K) break;
+          // an internal node: enter it where the ray meets its voxels' bounds, or pass it like an
+          // empty leaf if they lie behind tc or off the ray
+          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)child * 8);
+          const int4 n0 = np[0], n1 = np[1];
+          float c_in, c_out;
+          const bool hit = node_bounds(f, clo, s.nbox[child], c_in, c_out);
+          const float c_tc = fmaxf(tc, c_in);
+          if (!hit || !(c_tc < c_out)) {
+            child = kEmpty;
+            break;
+          }
+          tc = c_tc;
           ++depth;
           stk[depth * stride] = child;
           size = half;
           lo[0] = clo[0];
           lo[1] = clo[1];
           lo[2] = clo[2];
-          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)child * 8);
-          c0 = np[0];
-          c1 = np[1];
+          c0 = n0;
+          c1 = n1;
         }
         // (2) the leaf [clo, clo + half): report a voxel
         const float to = box_exit(f, clo, half);
@@ -311,7 +340,7 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
         // (3) advance and leave every node that no longer holds tc
         if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
         tc = to;
-        if (!(tc < cell_exit)) break;
+        if (!(tc < cell_end)) break;
         bool popped = false;
         while (depth > 0 && !(tc < box_exit(f, lo, size))) {
           --depth;

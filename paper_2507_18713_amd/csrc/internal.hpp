@@ -5,6 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "device.hpp"
 #include "salf.h"
 
@@ -14,12 +17,13 @@ namespace salf {
 salf_status set_error(salf_status code, const char* fmt, ...);
 salf_status check_hip(hipError_t e, const char* what);
 
-// ---- scene workspace layout: [root grid][skip grid][nodes][hash keys][hash values][2 temp grids][counters]
+// ---- scene workspace layout: [root grid][skip grid][nodes][node bounds][bounds scratch][hash keys]
+//      [hash values][2 temp grids][counters][activated corner values, pre-activated scenes only]
 struct SceneLayout {
   int64_t n_root;        // root cells
   int64_t node_cap;      // internal nodes the workspace can hold
   int64_t hash_cap;      // hash slots (power of two)
-  size_t root_off, skip_off, nodes_off, hkeys_off, hvals_off, tmp_off, counters_off;
+  size_t root_off, skip_off, nodes_off, nbox_off, box_tmp_off, hkeys_off, hvals_off, tmp_off, counters_off;
   size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
   size_t total;
 };
@@ -59,6 +63,19 @@ struct RenderParams {
 };
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream);
+
+// One request of a batched launch (sensor mode, corner field).  variant: bit 0 colour, bit 1
+// intensity, bit 2 pre-activated corner values.
+struct BatchItem {
+  RenderParams p;
+  int64_t tile_begin;  // first global tile (wave) of this request
+  int32_t variant;
+  int32_t pad;
+};
+// d_items: device array of n_items requests sorted by tile_begin (the first begins at 0);
+// d_counter: a zeroed device word the waves pull tiles from.
+hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
+                               hipStream_t stream);
 hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int32_t* counts, int32_t* ids,
                         float* t_in, float* t_out, hipStream_t stream);
 hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uint8_t* valid, hipStream_t stream);
@@ -72,4 +89,28 @@ struct BackwardParams {
 };
 hipError_t launch_backward(const BackwardParams& p, hipStream_t stream);
 
+// A registered scene (the context's registry).
+struct Scene {
+  bool live = false;
+  salf_scene_desc desc;
+  int64_t n = 0;
+  SceneLayout layout;
+  SceneView view;
+  BuildCounters counters;
+};
+
+}  // namespace salf
+
+struct salf_context {
+  int device = 0;
+  std::mutex mu;
+  std::vector<salf::Scene> scenes;
+};
+
+namespace salf {
+// Copy of a live scene's registry entry (under the context lock).  Errors: INVALID_ARG, NOT_FOUND.
+salf_status scene_snapshot(salf_context* ctx, int32_t scene_id, Scene* out);
+// Validation shared by the entry points.
+salf_status validate_sensor(const salf_sensor* s);
+salf_status validate_opts(const salf_render_opts* o);
 }  // namespace salf

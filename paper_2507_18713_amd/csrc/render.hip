@@ -119,12 +119,12 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
   return !(acc.T < t_min);
 }
 
-// The ray of this lane: its index and grid frame.  Returns false for lanes without a ray.
-__device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t& ray, float d[3], RayFrame& f) {
+// The ray of this lane of wave `wave` (tiled: the wave's 8x8 tile; else 64 consecutive rays): its
+// index and grid frame.  Returns false for lanes without a ray.
+__device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, int64_t& ray, float d[3], RayFrame& f) {
   const int lane = threadIdx.x & 63;
   int col = 0, row = 0;
   if (p.tiled) {
-    const int64_t wave = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
     const int tx = (int)(wave % p.tiles_x), ty = (int)(wave / p.tiles_x);
     col = tx * 8 + (lane & 7);
     row = ty * 8 + (lane >> 3);
@@ -132,7 +132,7 @@ __device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t& ray, fl
     ray = (int64_t)row * p.img_w + col;
     if (ray >= p.n) return false;
   } else {
-    ray = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    ray = wave * 64 + lane;
     if (ray >= p.n) return false;
   }
   float o[3];
@@ -155,12 +155,15 @@ __device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t& ray, fl
   return true;
 }
 
+// Render the rays of one wave (tile `wave` of p) and store their outputs.  stk: this lane's node
+// stack (stride kThreads).  Shared by the single-request kernel and the batched kernel, so a ray
+// renders to the same bits alone or in a batch.
 template <int FIELD, bool RGB, bool INT>
-__global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
+__device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk) {
   int64_t ray;
   float d[3];
   RayFrame f;
-  if (!lane_ray(p, ray, d, f)) return;
+  if (!lane_ray(p, wave, ray, d, f)) return;
   float sh[4] = {kShC0, kShC1 * d[0], kShC1 * d[1], kShC1 * d[2]};
   Accum acc;
   acc.T = 1.0f;
@@ -169,8 +172,7 @@ __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
   acc.n = 0;
   const int S = p.S;
   const float t_min = p.t_min;
-  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
-  traverse(p.scene, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
     return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, t_min, acc);
   });
   const salf_outputs& out = p.out;
@@ -183,6 +185,46 @@ __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
   if (out.intensity) out.intensity[ray] = acc.I;
   if (out.t_end) out.t_end[ray] = acc.T;
   if (out.n_hits) out.n_hits[ray] = acc.n;
+}
+
+template <int FIELD, bool RGB, bool INT>
+__global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  render_wave<FIELD, RGB, INT>(p, (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6, stk + threadIdx.x);
+}
+
+// Batched render of several requests in one launch: a grid sized to the GPU's resident capacity
+// whose waves pull global tile numbers from a counter until every tile of every request is done
+// (each wave's exit condition is that counter passing the tile count).  The request of a tile is
+// found by binary search over the requests' first tiles; its shading variant is uniform per wave.
+__global__ __launch_bounds__(kThreads) void render_batch_kernel(const BatchItem* items, int32_t n_items,
+                                                                int64_t n_tiles, uint32_t* counter) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1u);
+    const int64_t tile = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    if (tile >= n_tiles) break;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchItem& b = items[lo];
+    const int64_t w = tile - b.tile_begin;
+    switch (b.variant) {
+      case 0: render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x); break;
+      case 1: render_wave<SALF_FIELD_CORNER, true, false>(b.p, w, stk + threadIdx.x); break;
+      case 2: render_wave<SALF_FIELD_CORNER, false, true>(b.p, w, stk + threadIdx.x); break;
+      case 3: render_wave<SALF_FIELD_CORNER, true, true>(b.p, w, stk + threadIdx.x); break;
+      case 4: render_wave<kFieldCornerActivated, false, false>(b.p, w, stk + threadIdx.x); break;
+      case 5: render_wave<kFieldCornerActivated, true, false>(b.p, w, stk + threadIdx.x); break;
+      case 6: render_wave<kFieldCornerActivated, false, true>(b.p, w, stk + threadIdx.x); break;
+      default: render_wave<kFieldCornerActivated, true, true>(b.p, w, stk + threadIdx.x); break;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays r, int32_t max_hits, int32_t* counts,
@@ -244,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   int64_t ray;
   float dir[3];
   RayFrame f;
-  if (!lane_ray(p, ray, dir, f)) return;
+  if (!lane_ray(p, (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6, ray, dir, f)) return;
   const int32_t n_stop = p.out.n_hits[ray];
   if (n_stop <= 0) return;
   const float T_end = p.out.t_end[ray];
@@ -400,6 +442,24 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
   if (field == SALF_FIELD_PAPER) return launch_field<SALF_FIELD_PAPER>(p, blocks, stream);
   if (p.scene.act_geo != nullptr) return launch_field<kFieldCornerActivated>(p, blocks, stream);
   return launch_field<SALF_FIELD_CORNER>(p, blocks, stream);
+}
+
+hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
+                               hipStream_t stream) {
+  if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
+  static int resident_blocks = 0;  // blocks of this kernel the whole GPU keeps resident
+  if (resident_blocks == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_batch_kernel, kThreads, 0);
+    if (e != hipSuccess) return e;
+    resident_blocks = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const int64_t want = (n_tiles + 3) / 4;  // 4 waves per block
+  const unsigned blocks = (unsigned)(want < resident_blocks ? want : resident_blocks);
+  render_batch_kernel<<<blocks, kThreads, 0, stream>>>(d_items, n_items, n_tiles, d_counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_backward(const BackwardParams& b, hipStream_t stream) {

@@ -57,6 +57,8 @@ struct BuildArgs {
   int64_t hcap;
   int64_t node_cap;
   BuildCounters* cnt;
+  int32_t* box_tmp;  // [node_cap][6] absolute finest bounds of each node's voxels (min lo, max hi)
+  uint2* nbox;       // [node_cap] packed bounds relative to the node
 };
 
 __device__ __forceinline__ void report(BuildCounters* c, int bit, int32_t v) {
@@ -154,6 +156,16 @@ __global__ void link_kernel(BuildArgs a) {
       report(a.cnt, 2, (int32_t)v);
       return;
     }
+    if (m < l) {  // grow the ancestor's bounds of occupied content by this voxel
+      const int sh_f = a.K - l;
+      const int32_t vlo[3] = {q.y << sh_f, q.z << sh_f, q.w << sh_f};
+      int32_t* b = a.box_tmp + (int64_t)value * 6;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        atomicMin(&b[ax], vlo[ax]);
+        atomicMax(&b[3 + ax], vlo[ax] + (1 << sh_f));
+      }
+    }
     parent = value;
   }
 }
@@ -183,6 +195,37 @@ __global__ void skip_pass(const int32_t* root, const uint8_t* in, uint8_t* out, 
     best = v < best ? v : best;
   }
   out[i] = (uint8_t)best;
+}
+
+__global__ void box_init(int32_t* b, int64_t n_nodes) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_nodes; i += (int64_t)gridDim.x * blockDim.x) {
+    b[i * 6 + 0] = b[i * 6 + 1] = b[i * 6 + 2] = 0x7fffffff;
+    b[i * 6 + 3] = b[i * 6 + 4] = b[i * 6 + 5] = -0x7fffffff;
+  }
+}
+
+// Pack every node's bounds relative to the node's min corner: bytes (lo_x, lo_y, lo_z) and
+// (hi_x - 1, hi_y - 1, hi_z - 1), each in [0, 255] since a node spans at most 2^K <= 256 cells.
+// The node's own box comes from its hash key (depth, coordinates at that depth).
+__global__ void box_pack(BuildArgs a) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h >= a.hcap) return;
+  const uint64_t key = a.hkeys[h];
+  if (key == kNoKey) return;
+  const int32_t id = a.hvals[h];
+  if (id < 0) return;
+  const int depth = (int)(key >> 60);
+  const int sh = a.K - depth;
+  const int32_t nlo[3] = {(int32_t)((key >> 40) & 0xFFFFF) << sh, (int32_t)((key >> 20) & 0xFFFFF) << sh,
+                          (int32_t)(key & 0xFFFFF) << sh};
+  const int32_t* b = a.box_tmp + (int64_t)id * 6;
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    lo |= (uint32_t)(b[ax] - nlo[ax]) << (8 * ax);
+    hi |= (uint32_t)(b[3 + ax] - 1 - nlo[ax]) << (8 * ax);
+  }
+  a.nbox[id] = make_uint2(lo, hi);
 }
 
 __global__ void count_roots(const int32_t* root, int64_t n, BuildCounters* c) {
@@ -225,6 +268,10 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   off = up(off + (size_t)n_root);
   L->nodes_off = off;
   off = up(off + (size_t)node_cap * 32);
+  L->nbox_off = off;
+  off = up(off + (size_t)node_cap * 8);
+  L->box_tmp_off = off;
+  off = up(off + (size_t)node_cap * 24);
   L->hkeys_off = off;
   off = up(off + (size_t)hcap * 8);
   L->hvals_off = off;
@@ -280,14 +327,19 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   a.hcap = L.hash_cap;
   a.node_cap = L.node_cap;
   a.cnt = (BuildCounters*)(base + L.counters_off);
+  a.box_tmp = (int32_t*)(base + L.box_tmp_off);
+  a.nbox = (uint2*)(base + L.nbox_off);
   const int T = 256;
   fill_i32<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.root, kEmpty, L.n_root);
+  if (L.node_cap > 0) box_init<<<blocks_for(L.node_cap, T) > 8192 ? 8192 : blocks_for(L.node_cap, T), T, 0, stream>>>(
+      a.box_tmp, L.node_cap);
   if (L.node_cap > 0) fill_i32<<<blocks_for(L.node_cap * 8, T), T, 0, stream>>>(a.nodes, kEmpty, L.node_cap * 8);
   fill_u64<<<blocks_for(L.hash_cap, T), T, 0, stream>>>(a.hkeys, kNoKey, L.hash_cap);
   init_counters<<<1, 64, 0, stream>>>(a.cnt);
   if (n > 0) insert_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
   number_kernel<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
   if (n > 0) link_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
+  box_pack<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
   {
     uint8_t* skip = (uint8_t*)(base + L.skip_off);
     uint8_t* t0 = (uint8_t*)(base + L.tmp_off);

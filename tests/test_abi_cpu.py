@@ -49,6 +49,8 @@ int main(void) {
   printf("RenderOpts %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, reserved));
   printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
+  printf("ServerOpts %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight));
+  printf("ServerStats %zu %zu\n", sizeof(salf_server_stats), offsetof(salf_server_stats, inflight));
   return 0;
 }
 """
@@ -68,6 +70,8 @@ int main(void) {
         "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.reserved.offset],
         "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
+        "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset],
+        "ServerStats": [C.sizeof(S.ServerStats), S.ServerStats.inflight.offset],
     }
     assert got == want
 
@@ -118,6 +122,30 @@ def test_sensor_ray_count_host_logic(L):
     assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
     bad = dict(synth.config1_camera(), t_near=2.0, t_far=1.0)
     assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
+
+
+def test_server_sizes_host_logic(L):
+    from paper_2507_18713_amd.api import sensor_struct
+    import synth
+    lib = L.lib()
+    n = C.c_size_t()
+    op = L.ServerOpts()
+    op.max_batch, op.max_inflight = 64, 2
+    assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == 0
+    two = n.value
+    op.max_batch = 128
+    assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == 0 and n.value > two > 2 * 64 * 256
+    for mb, mi in ((0, 2), (257, 2), (64, 0), (64, 5)):
+        op.max_batch, op.max_inflight = mb, mi
+        assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == -1
+    cam = sensor_struct(synth.config1_camera())
+    assert lib.salf_server_request_bytes(C.byref(cam), 1 | 2 | 4, C.byref(n)) == 0
+    px = 1920 * 1080
+    assert n.value == sum((b + 255) // 256 * 256 for b in (px * 12, px * 4, px * 4))
+    assert lib.salf_server_request_bytes(C.byref(cam), 0, C.byref(n)) == -1
+    assert lib.salf_server_request_bytes(C.byref(cam), 16, C.byref(n)) == -1
+    assert lib.salf_server_create(None, None, None) == -1
+    assert lib.salf_server_destroy(None) == -1
 
 
 def test_null_arguments_are_rejected(L):

@@ -1,0 +1,110 @@
+"""Continuous-batching server on the GPU: each request's outputs in a batched mix equal the same
+request rendered alone (bit for bit: the same device function renders a tile in both), admission
+never exceeds the pool, every ray of every request is written, and errors are reported."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+from test_gpu_render import dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def salf():
+    import paper_2507_18713_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def scenes(salf):
+    a = synth.random_scene(201, root_dims=(8, 6, 3), max_level=2)
+    b = synth.random_scene(202, root_dims=(6, 8, 4), max_level=3, origin=(-3.0, -4.0, -1.0))
+    return [salf.Scene.from_data(a, device=dev()), salf.Scene.from_data(b, device=dev(), preactivate=True),
+            salf.Scene.from_data(a, device=dev(), preactivate=True)]
+
+
+def _sensors():
+    """An uneven mix: pinholes and fisheyes with rolling shutter, LiDARs, tiny and ragged sizes."""
+    out = []
+    for i in range(6):
+        eye = (7.0 * np.cos(i), 6.0 * np.sin(i), 2.0 + 0.3 * i)
+        out.append(("cam", synth.pinhole(40 + 17 * i, 24 + 9 * i, 70.0, synth.look_at(eye, (0, 0, 0)), eye,
+                                        dt_line=1e-4 * i, v=(3.0, 0, 0), w=(0, 0, 0.2 * i))))
+    out.append(("cam", synth.fisheye_equidistant(64, 48, 190.0, synth.look_at((0.2, 0.1, 0.3), (1, 0, 0)),
+                                                 (0.2, 0.1, 0.3), dt_line=3e-5)))
+    out.append(("lid", synth.lidar_spinning(32, 256, -25, 15, np.eye(3), (0.1, 0.2, 0.4), 0.1, v=(10, 0, 0))))
+    out.append(("lid", synth.lidar_spinning(16, 100, -25, 15, synth.yaw_lidar(40.0), (-0.5, 0.3, 0.2), 0.1)))
+    out.append(("cam", synth.pinhole(1, 1, 30.0, synth.look_at((5, 5, 5), (0, 0, 0)), (5, 5, 5))))
+    return out
+
+
+OUTS = {"cam": ("rgb", "depth", "opacity"), "lid": ("depth", "intensity", "opacity")}
+
+
+def test_mix_equals_alone_and_every_ray_is_written(salf, scenes):
+    srv = salf.Server(pool_bytes=64 << 20, device=dev(), max_batch=8, max_inflight=2)
+    srv.pool.fill_(255)  # NaN bit patterns everywhere: a ray the kernel skipped stays NaN
+    torch.cuda.synchronize()
+    jobs = []
+    for rep in range(3):
+        for j, (kind, s) in enumerate(_sensors()):
+            sc = scenes[(j + rep) % len(scenes)]
+            jobs.append((srv.submit(sc, s, outputs=OUTS[kind]), sc, s, kind))
+    for tk, _, _, _ in jobs:
+        assert srv.wait(tk, timeout=60.0)
+    for tk, sc, s, kind in jobs:
+        res, t_sub, t_done = srv.poll(tk)
+        assert t_done >= t_sub > 0
+        alone = salf.render(sc, sensor=s, outputs=OUTS[kind])
+        for k in OUTS[kind]:
+            assert not torch.any(torch.isnan(res[k])), k
+            assert torch.equal(res[k], alone[k]), (kind, k)
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["launches"] >= 2 and st["pool_peak"] <= 64 << 20
+    for tk, _, _, _ in jobs:
+        srv.release(tk)
+    assert srv.stats()["pool_in_use"] == 0
+    srv.close()
+
+
+def test_admission_respects_the_budget_in_order(salf, scenes):
+    cam = synth.pinhole(160, 120, 70.0, synth.look_at((7, -6, 4), (0, 0, 0)), (7, -6, 4))
+    need = salf.Server.request_bytes(cam)
+    pool = 2 * need + 1024  # room for two requests at a time
+    srv = salf.Server(pool_bytes=pool, device=dev(), max_batch=4, max_inflight=2)
+    tks = [srv.submit(scenes[0], cam) for _ in range(7)]
+    finished = []
+    t0 = time.monotonic()
+    while len(finished) < len(tks) and time.monotonic() - t0 < 60:
+        for tk in tks:
+            if tk in finished:
+                continue
+            r = srv.poll(tk)
+            if r is not None:
+                st = srv.stats()
+                assert st["pool_in_use"] <= pool
+                finished.append(tk)
+                srv.release(tk)
+        time.sleep(0.001)
+    assert sorted(finished) == tks
+    st = srv.stats()
+    assert st["pool_peak"] <= pool and st["pool_peak"] >= need
+    with pytest.raises(salf.SalfError, match="BUDGET"):
+        srv.submit(scenes[0], synth.pinhole(400, 400, 70.0, np.eye(3), (0, 0, 0)))
+    with pytest.raises(salf.SalfError, match="NOT_FOUND"):
+        srv.release(123456789)
+    srv.close()
+
+
+def test_paper_field_scene_is_refused(salf):
+    data = synth.random_scene(203)
+    sc = salf.Scene.from_data(data, device=dev(), field="paper")
+    srv = salf.Server(pool_bytes=1 << 20, device=dev())
+    with pytest.raises(salf.SalfError, match="UNSUPPORTED"):
+        srv.submit(sc, synth.pinhole(8, 8, 60.0, np.eye(3), (0, 0, -5)))
+    srv.close()
