@@ -228,6 +228,80 @@ def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1
             "poisson": points, "server_launches": st["launches"], "server_pool_peak": st["pool_peak"]}
 
 
+# ------------------------------------------------------------------ training step (differentiation)
+def training_bench(salf, torch, dev, data, steps=10, seed=4):
+    """1,048,576 rays per batch on the driving scene: 80% camera pixels drawn from 8 random views,
+    20% LiDAR rays from 2 sweeps; loss = mean squared colour error + mean absolute depth error
+    against targets rendered from a perturbed copy (logits + N(0, 0.1^2)).  A step = zero the
+    gradients, forward, loss gradients, hand-written backward."""
+    import numpy as np
+
+    import synth
+    rng = np.random.default_rng(seed)
+    scene = salf.Scene.from_data(data, device=dev)
+    pert = synth.SceneData(**{**data.__dict__})
+    prng = np.random.default_rng(5)
+    pert.z_geo = (data.z_geo + prng.normal(0, 0.1, data.z_geo.shape)).astype(np.float32)
+    pert.z_rgb = (data.z_rgb + prng.normal(0, 0.1, data.z_rgb.shape)).astype(np.float32)
+    pert.z_int = (data.z_int + prng.normal(0, 0.1, data.z_int.shape)).astype(np.float32)
+    target_scene = salf.Scene.from_data(pert, device=dev)
+    n_cam, n_lid = 838861, 209715
+    oc, dc = [], []
+    for _ in range(8):
+        x, y = rng.uniform(-80, 80), rng.uniform(-3, 3)
+        yaw = rng.uniform(-30, 30) + (0.0 if rng.random() < 0.5 else 180.0)
+        r = salf.generate_rays(synth.pinhole(1920, 1080, 60.0, synth.yaw_pitch_camera(yaw, -5.0), (x, y, 1.6)), dev)
+        oc.append(r["o"])
+        dc.append(r["d"])
+    oc, dc = torch.cat(oc), torch.cat(dc)
+    ic = torch.from_numpy(np.sort(rng.choice(oc.shape[0], n_cam, replace=False))).to(dev)
+    ol, dl = [], []
+    for x in (-60.0, 20.0):
+        r = salf.generate_rays(synth.lidar_spinning(64, 2048, -25, 15, np.eye(3), (x, 0.37, 1.85), 0.1, v=(10, 0, 0)),
+                               dev)
+        ol.append(r["o"])
+        dl.append(r["d"])
+    ol, dl = torch.cat(ol), torch.cat(dl)
+    il = torch.from_numpy(np.sort(rng.choice(ol.shape[0], n_lid, replace=False))).to(dev)
+    oc, dc = oc[ic].contiguous(), dc[ic].contiguous()
+    ol, dl = ol[il].contiguous(), dl[il].contiguous()
+    opts = dict(samples=4, t_min=1e-6)
+    tgt_c = salf.render(target_scene, o=oc, d=dc, outputs=("rgb",), **opts)["rgb"]
+    tgt_d = salf.render(target_scene, o=ol, d=dl, outputs=("depth",), **opts)["depth"]
+    d_geo, d_rgb, d_int = (torch.zeros_like(t) for t in (scene.geo, scene.rgb, scene.intensity))
+    saved_outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
+
+    def step():
+        d_geo.zero_()
+        d_rgb.zero_()
+        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, **opts)
+        fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), **opts)
+        g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
+        g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
+        salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
+        salf.render_backward(scene, fl, {"depth": g_l}, o=ol, d=dl, d_geo=d_geo, **opts)
+        return fc, fl
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fc, fl = step()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
+    ms = float(np.median(times))
+    return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
+                        "L2 colour + L1 depth vs a perturbed copy",
+            "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
+            "mrays_s_fwd_bwd": round((n_cam + n_lid) / ms / 1e3, 2), "loss": round(loss, 5),
+            "grad_abs_sum": float(d_geo.abs().sum() + d_rgb.abs().sum())}
+
+
 # ------------------------------------------------------------------ GPU
 def main():
     ap = argparse.ArgumentParser()
@@ -236,6 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--serve-ticks", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -356,6 +431,8 @@ def main():
         "scene_generate_s": round(t_gen, 2),
         "kernel_source_hash": kernel_source_hash(),
     }
+    if not args.no_training:
+        rec["training"] = training_bench(salf, torch, dev, data)
     if not args.no_serving:
         rec["serving"] = serving_bench(salf, torch, dev, n_ticks=args.serve_ticks)
         rec["metric"] = "Mrays/s camera+LiDAR render on 1 GPU; p50/p99 frame latency served vs plain"
