@@ -271,97 +271,33 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     d_geo, d_rgb, d_int = (torch.zeros_like(t) for t in (scene.geo, scene.rgb, scene.intensity))
     saved_outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
 
-    def step():
-        d_geo.zero_()
-        d_rgb.zero_()
-        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, **opts)
-        fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), **opts)
-        g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
-        g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
-        salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
-        salf.render_backward(scene, fl, {"depth": g_l}, o=ol, d=dl, d_geo=d_geo, **opts)
-        return fc, fl
-
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        fc, fl = step()
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
-    ms = float(np.median(times))
-    return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
-                        "L2 colour + L1 depth vs a perturbed copy",
-            "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
-            "mrays_s_fwd_bwd": round((n_cam + n_lid) / ms / 1e3, 2), "loss": round(loss, 5),
-            "grad_abs_sum": float(d_geo.abs().sum() + d_rgb.abs().sum())}
-
-
-# ------------------------------------------------------------------ GPU
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-training", action="store_true")
-    ap.add_argument("--serve-ticks", type=int, default=40)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path runs on a single "
-              f"GPU; sharding across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_2507_18713_amd as salf
-    import synth
-
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    t0 = time.perf_counter()
-    data = synth.config1_scene()
-    t_gen = time.perf_counter() - t0
-    # forward renders read the activated corner values stored at upload (the workload's corner
-    # values are softplus / sigmoid of the drawn logits); the raw-logit scene is timed beside it
-    scene = salf.Scene.from_data(data, device=dev, preactivate=True)
-    raw_scene = salf.Scene.from_data(data, device=dev)
-    torch.cuda.synchronize()
-    # scene build time alone (upload excluded)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    scene2 = salf.Scene(scene._voxels, scene.geo, scene.rgb, scene.intensity, data.origin, data.root_size,
-                        data.root_dims, data.max_level, preactivate=True)
-    e1.record()
-    torch.cuda.synchronize()
-    build_ms = e0.elapsed_time(e1)
-    scene2.destroy()
-    del scene2
-
-    cam = synth.config1_camera()
-    lid = synth.config2_lidar()
-    n_cam, n_lid = cam["width"] * cam["height"], lid["width"] * lid["height"]
-    opts = dict(samples=4, t_min=1e-6)
-    cam_out = {"rgb": torch.empty((n_cam, 3), device=dev), "depth": torch.empty(n_cam, device=dev),
-               "opacity": torch.empty(n_cam, device=dev)}
-    lid_out = {k: torch.empty(n_lid, device=dev) for k in ("depth", "intensity", "opacity")}
-
     def step(ev=None):
+        # the LiDAR sweep of a step runs on a second stream beside its camera frame; a step
+        # starts once the previous step's two renders have finished.  ev: events recorded around
+        # the camera render (main stream) and the LiDAR render (second stream)
+        side_stream.wait_stream(main_stream)
         if ev is not None:
-            ev[0].record()
+            ev[0].record(main_stream)
         salf.render(scene, sensor=cam, outputs=cam_out.keys(), out=cam_out, **opts)
         if ev is not None:
-            ev[1].record()
-        salf.render(scene, sensor=lid, outputs=lid_out.keys(), out=lid_out, **opts)
-        if ev is not None:
-            ev[2].record()
+            ev[1].record(main_stream)
+        with torch.cuda.stream(side_stream):
+            if ev is not None:
+                ev[2].record(side_stream)
+            salf.render(scene, sensor=lid, outputs=lid_out.keys(), out=lid_out, **opts)
+            if ev is not None:
+                ev[3].record(side_stream)
+        main_stream.wait_stream(side_stream)
+
+    def kernel_ms(sensor, outs):
+        """Average duration of one render alone, by HIP events on the stream it runs on."""
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, **opts)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
 
     # instrumented run (not timed): shaded hits per ray for the algorithmic byte count
     hc = salf.render(scene, sensor=cam, outputs=("n_hits",), **opts)["n_hits"]
@@ -371,17 +307,22 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     t_start = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    # per-launch durations inside the timed region (each render shares the GPU with the other)
     cam_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    lid_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-    step_ms = sum(e[0].elapsed_time(e[2]) for e in evs) / args.steps
+    lid_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    # steady-state period: camera start to camera start (steps are serialized by the stream waits)
+    step_ms = evs[0][0].elapsed_time(evs[-1][0]) / (args.steps - 1) if args.steps > 1 else None
     rays = n_cam + n_lid
     value = rays / (wall / args.steps) / 1e6
+    # each render alone, after the timed region
+    cam_alone_ms = kernel_ms(cam, cam_out) if args.alone else None
+    lid_alone_ms = kernel_ms(lid, lid_out) if args.alone else None
 
     # the same camera frame from the raw-logit scene (corner activations evaluated per hit)
     e0.record()
@@ -420,13 +361,16 @@ def main():
             "traffic": traffic,
         },
         "camera": {"ms": round(cam_ms, 4), "mrays_s": round(n_cam / cam_ms / 1e3, 2),
+                   "ms_alone": None if cam_alone_ms is None else round(cam_alone_ms, 4),
                    "ms_raw_logit_scene": round(cam_raw_ms, 4),
                    "shaded_hits_per_ray": round(hits_cam / n_cam, 3), "algorithmic_bytes": cam_bytes},
         "lidar": {"ms": round(lid_ms, 4), "mrays_s": round(n_lid / lid_ms / 1e3, 2),
+                  "ms_alone": None if lid_alone_ms is None else round(lid_alone_ms, 4),
                   "shaded_hits_per_ray": round(hits_lid / n_lid, 3), "algorithmic_bytes": lid_bytes,
                   "achieved_GBs": round(lid_bytes / (lid_ms * 1e-3) / 1e9, 1),
-                  "sweeps_per_s": round(1e3 / lid_ms, 1)},
-        "event_ms_per_step": round(step_ms, 4),
+                  "sweeps_per_s_alone": None if lid_alone_ms is None else round(1e3 / lid_alone_ms, 1)},
+        "event_ms_per_step": None if step_ms is None else round(step_ms, 4),
+        "step": "camera frame and LiDAR sweep rendered concurrently on two streams",
         "scene_build_ms": round(build_ms, 3),
         "scene_generate_s": round(t_gen, 2),
         "kernel_source_hash": kernel_source_hash(),

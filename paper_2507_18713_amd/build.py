@@ -22,8 +22,11 @@ SOURCES = ["api.hip", "scene_build.hip", "render.hip", "server.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: no packed FP32 VALU instructions (kept scalar on purpose).
+# -ffp-contract=off: no implicit multiply-add fusion, so a ray's arithmetic rounds the same way in
+# every kernel that renders it (fused ray generation or explicit rays, alone or in a batch); the
+# fused multiply-adds of the hot loops are written out with fmaf.
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
 ]

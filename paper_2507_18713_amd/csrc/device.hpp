@@ -213,19 +213,26 @@ struct Hit {
 // Sample geometry of a hit segment: the position at t_in relative to the voxel's min corner and
 // the step between samples, in finest cells, formed in FP64 from the FP32 ray and then kept in
 // FP32 (small numbers, so far-away samples keep full precision); the piece length delta and the
-// scale sc to local coordinates x = (rel + (k + 1/2) stp) sc - 1.
-__device__ __forceinline__ void segment_frame(const SceneView& s, const RayFrame& f, const Hit& h, int S,
+// scale sc = 1 / size to unit-cube coordinates u = (rel + (k + 1/2) stp) sc, u = (x + 1) / 2 for
+// the local x in [-1, 1].  rS = 1 / S.
+__device__ __forceinline__ void segment_frame(const SceneView& s, const RayFrame& f, const Hit& h, double rS,
                                               float rel[3], float stp[3], float& delta, float& sc) {
-  const double dt = (double)h.t_out - (double)h.t_in;
-  delta = (float)(dt / S);
+  const double ti = (double)h.t_in;
+  const double dtS = ((double)h.t_out - ti) * rS;
+  delta = (float)dtS;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double ogd = ((double)f.o[a] - s.org[a]) * s.gs;
     const double dgd = (double)f.d[a] * s.gs;
-    rel[a] = (float)((ogd - (double)h.lo[a]) + (double)h.t_in * dgd);
-    stp[a] = (float)(dt * dgd / S);
+    rel[a] = (float)fma(ti, dgd, ogd - (double)h.lo[a]);
+    stp[a] = (float)(dtS * dgd);
   }
-  sc = 2.0f / (float)h.size;
+  sc = __builtin_amdgcn_rcpf((float)h.size);  // exact: size is a power of two
+}
+
+// Unit-cube coordinate of sample k (midpoint k + 1/2) along one axis, clamped to [0, 1].
+__device__ __forceinline__ float sample_u(float rel, float stp, float fk, float sc) {
+  return __builtin_amdgcn_fmed3f(fmaf(fk, stp, rel) * sc, 0.0f, 1.0f);
 }
 
 // Front-to-back walk over the voxels a ray hits: calls visit(hit) for each, in increasing t_in,
@@ -450,16 +457,25 @@ __device__ inline bool sensor_ray(const salf_sensor& s, int col, int row, float 
 }
 
 // ----------------------------------------------------------------------------- fields
+// Dot product of trilinear weights with 8 corner values, as a chain of fused multiply-adds.
+__device__ __forceinline__ float dot8(const float w[8], const float c[8]) {
+  float a = w[0] * c[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) a = fmaf(w[i], c[i], a);
+  return a;
+}
+
 __device__ __forceinline__ float softplus_f(float z) {
   return fmaxf(z, 0.0f) + __logf(1.0f + __expf(-fabsf(z)));
 }
 __device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
-// Trilinear corner weights at x in [-1, 1]^3 (corner c = bx + 2 by + 4 bz).
-__device__ __forceinline__ void corner_weights(const float x[3], float w[8]) {
-  const float lx = 0.5f - 0.5f * x[0], hx = 0.5f + 0.5f * x[0];
-  const float ly = 0.5f - 0.5f * x[1], hy = 0.5f + 0.5f * x[1];
-  const float lz = 0.5f - 0.5f * x[2], hz = 0.5f + 0.5f * x[2];
+// Trilinear corner weights at unit-cube coordinates u in [0, 1]^3 (u = (x + 1) / 2 for the local
+// x in [-1, 1]; corner c = bx + 2 by + 4 bz).
+__device__ __forceinline__ void corner_weights(const float u[3], float w[8]) {
+  const float hx = u[0], lx = 1.0f - hx;
+  const float hy = u[1], ly = 1.0f - hy;
+  const float hz = u[2], lz = 1.0f - hz;
   const float a0 = ly * lz, a1 = hy * lz, a2 = ly * hz, a3 = hy * hz;
   w[0] = lx * a0; w[1] = hx * a0; w[2] = lx * a1; w[3] = hx * a1;
   w[4] = lx * a2; w[5] = hx * a2; w[6] = lx * a3; w[7] = hx * a3;

@@ -24,6 +24,7 @@ struct SceneLayout {
   int64_t node_cap;      // internal nodes the workspace can hold
   int64_t hash_cap;      // hash slots (power of two)
   size_t root_off, skip_off, nodes_off, nbox_off, box_tmp_off, hkeys_off, hvals_off, tmp_off, counters_off;
+  size_t order_off;  // node-numbering temporaries (0 when the scene can have no nodes)
   size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
   size_t total;
 };

@@ -22,7 +22,7 @@ struct Accum {
 // become opaque enough to stop (T < t_min after the voxel).
 template <int FIELD, bool RGB, bool INT>
 __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
-                                            int S, float t_min, Accum& acc) {
+                                            int S, double rS, float t_min, Accum& acc) {
   const int32_t v = h.voxel;
   const float ti = h.t_in;
   // corner parameters of the voxel (coalescing across lanes comes from coherent rays)
@@ -66,53 +66,48 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
     }
   } else if (FIELD == SALF_FIELD_PAPER && RGB) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) shc[ch] = c[ch][3] * sh[0] + c[ch][4] * sh[1] + c[ch][5] * sh[2] + c[ch][6] * sh[3];
+    for (int ch = 0; ch < 3; ++ch)
+      shc[ch] = fmaf(c[ch][3], sh[0], fmaf(c[ch][4], sh[1], fmaf(c[ch][5], sh[2], c[ch][6] * sh[3])));
   }
 
   float rel[3], stp[3], delta, sc;
-  segment_frame(s, f, h, S, rel, stp, delta, sc);
+  segment_frame(s, f, h, rS, rel, stp, delta, sc);
 
   for (int k = 0; k < S; ++k) {
     const float fk = (float)k + 0.5f;
-    float x[3];
+    float u[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = fminf(fmaxf((rel[a] + fk * stp[a]) * sc - 1.0f, -1.0f), 1.0f);
+    for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
     float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
     if (FIELD != SALF_FIELD_PAPER) {
       float w[8];
-      corner_weights(x, w);
-      sigma = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sigma += w[i] * g[i];
+      corner_weights(u, w);
+      sigma = dot8(w, g);
       if (RGB) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          float a = 0.0f;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) a += w[i] * c[ch][i];
-          col[ch] = a;
-        }
+        for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, c[ch]);
       }
-      if (INT) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) inten += w[i] * it[i];
-      }
+      if (INT) inten = dot8(w, it);
     } else {
-      sigma = __expf(g[0] * x[0] + g[1] * x[1] + g[2] * x[2] + g[3]);
+      float x[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
+      sigma = __expf(fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3]))));
       if (RGB) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = sigmoid_f(c[ch][0] * x[0] + c[ch][1] * x[1] + c[ch][2] * x[2] + shc[ch]);
+        for (int ch = 0; ch < 3; ++ch)
+          col[ch] = sigmoid_f(fmaf(c[ch][0], x[0], fmaf(c[ch][1], x[1], fmaf(c[ch][2], x[2], shc[ch]))));
       }
-      if (INT) inten = sigmoid_f(it[0] * x[0] + it[1] * x[1] + it[2] * x[2] + it[3]);
+      if (INT) inten = sigmoid_f(fmaf(it[0], x[0], fmaf(it[1], x[1], fmaf(it[2], x[2], it[3]))));
     }
     const float e = __expf(-sigma * delta);
     const float wgt = acc.T * (1.0f - e);
     if (RGB) {
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc.C[ch] += wgt * col[ch];
+      for (int ch = 0; ch < 3; ++ch) acc.C[ch] = fmaf(wgt, col[ch], acc.C[ch]);
     }
-    acc.D += wgt * (ti + fk * delta);
-    if (INT) acc.I += wgt * inten;
+    acc.D = fmaf(wgt, fmaf(fk, delta, ti), acc.D);
+    if (INT) acc.I = fmaf(wgt, inten, acc.I);
     acc.T *= e;
   }
   acc.n += 1;
@@ -171,14 +166,15 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   acc.D = acc.I = 0.0f;
   acc.n = 0;
   const int S = p.S;
+  const double rS = 1.0 / S;
   const float t_min = p.t_min;
   traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
-    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, t_min, acc);
+    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
   });
   const salf_outputs& out = p.out;
   if (out.rgb) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = acc.C[ch] + acc.T * p.bg[ch];
+    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = fmaf(acc.T, p.bg[ch], acc.C[ch]);
   }
   if (out.depth) out.depth[ray] = acc.D;
   if (out.opacity) out.opacity[ray] = 1.0f - acc.T;
@@ -305,6 +301,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const float gOT = (b.g.d_opacity ? b.g.d_opacity[ray] : 0.0f) * T_end;
   const SceneView& s = p.scene;
   const int S = p.S;
+  const double rS = 1.0 / S;
   float T = 1.0f, PC[3] = {0.0f, 0.0f, 0.0f}, PD = 0.0f, PI = 0.0f;
   int32_t count = 0;
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
@@ -338,7 +335,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       for (int i = 0; i < 8; ++i) ci[i] = sigmoid_f(zi[i]);
     }
     float rel[3], stp[3], delta, sc;
-    segment_frame(s, f, h, S, rel, stp, delta, sc);
+    segment_frame(s, f, h, rS, rel, stp, delta, sc);
     float ag[8], ar[3][8], ai[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -348,59 +345,51 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     }
     for (int k = 0; k < S; ++k) {
       const float fk = (float)k + 0.5f;
-      float x[3], w[8];
+      float u[3], w[8];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) x[a] = fminf(fmaxf((rel[a] + fk * stp[a]) * sc - 1.0f, -1.0f), 1.0f);
-      corner_weights(x, w);
-      float sigma = 0.0f, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sigma += w[i] * sp[i];
+      for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
+      corner_weights(u, w);
+      // the forward's arithmetic, operation for operation, so T and the prefix sums match it
+      const float sigma = dot8(w, sp);
+      float col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
       if (RGB) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          float a = 0.0f;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) a += w[i] * cr[ch][i];
-          col[ch] = a;
-        }
+        for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, cr[ch]);
       }
-      if (INT) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) inten += w[i] * ci[i];
-      }
+      if (INT) inten = dot8(w, ci);
       const float e = __expf(-sigma * delta);
       const float wgt = T * (1.0f - e);
       const float Tn = T * e;
-      const float tk = ti + fk * delta;
+      const float tk = fmaf(fk, delta, ti);
       float dtau = gOT;
       if (RGB) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-          PC[ch] += wgt * col[ch];
-          dtau += gC[ch] * (Tn * col[ch] - (Cs[ch] - PC[ch]));
+          PC[ch] = fmaf(wgt, col[ch], PC[ch]);
+          dtau = fmaf(gC[ch], fmaf(Tn, col[ch], -(Cs[ch] - PC[ch])), dtau);
         }
       }
-      PD += wgt * tk;
-      dtau += gD * (Tn * tk - (Ds - PD));
+      PD = fmaf(wgt, tk, PD);
+      dtau = fmaf(gD, fmaf(Tn, tk, -(Ds - PD)), dtau);
       if (INT) {
-        PI += wgt * inten;
-        dtau += gI * (Tn * inten - (Is - PI));
+        PI = fmaf(wgt, inten, PI);
+        dtau = fmaf(gI, fmaf(Tn, inten, -(Is - PI)), dtau);
       }
       const float dsig = dtau * delta;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) ag[i] += dsig * w[i];
+      for (int i = 0; i < 8; ++i) ag[i] = fmaf(dsig, w[i], ag[i]);
       if (RGB) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
           const float gw = gC[ch] * wgt;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) ar[ch][i] += gw * w[i];
+          for (int i = 0; i < 8; ++i) ar[ch][i] = fmaf(gw, w[i], ar[ch][i]);
         }
       }
       if (INT) {
         const float gw = gI * wgt;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) ai[i] += gw * w[i];
+        for (int i = 0; i < 8; ++i) ai[i] = fmaf(gw, w[i], ai[i]);
       }
       T = Tn;
     }

@@ -2,11 +2,16 @@
 // level-0 voxel or an 8-ary octree, whose non-leaf nodes point to their 8 sub-volumes and whose
 // leaves hold "empty" or a voxel (Sec. 3.2, octree ray casting).
 //
-// Build, one thread per voxel, four kernels:
+// Build, one thread per voxel or hash slot:
 //   1. fill: root grid and node children <- empty, hash keys <- unused
 //   2. insert: validate each voxel (level and coordinates in range) and insert the keys of its
-//      ancestors (depth m = 0 .. l-1, coordinates >> (l - m)) into an open-addressing hash set
-//   3. number: every occupied hash slot receives a node index
+//      ancestors (depth m = 0 .. l-1, coordinates >> (l - m)) into an open-addressing hash set,
+//      keeping per node the smallest index of a voxel below it (its first voxel)
+//   3. number: nodes are numbered in the order (first voxel, depth).  The nodes whose first voxel
+//      is v are ancestors of v at consecutive depths d0(v) .. l_v - 1, so a node's index is
+//      offset(v) + depth - d0(v), with offset an exclusive scan of the counts l_v - d0(v).  For
+//      voxels uploaded in Morton order of their corners this is the depth-first pre-order of every
+//      octree (siblings' subtrees are contiguous), and for any order it is deterministic.
 //   4. link: write each ancestor's index into its parent's child slot (or the root grid) and the
 //      voxel's leaf code into its own slot, all by compare-and-swap from "empty".  Two voxels that
 //      overlap or repeat make two different values compete for one slot; the loser is reported.
@@ -59,6 +64,8 @@ struct BuildArgs {
   BuildCounters* cnt;
   int32_t* box_tmp;  // [node_cap][6] absolute finest bounds of each node's voxels (min lo, max hi)
   uint2* nbox;       // [node_cap] packed bounds relative to the node
+  int32_t* d0;       // [n] shallowest depth of a node whose first voxel is v (numbering only)
+  int32_t* offs;     // [n] first node index of those nodes (numbering only)
 };
 
 __device__ __forceinline__ void report(BuildCounters* c, int bit, int32_t v) {
@@ -71,15 +78,16 @@ __device__ __forceinline__ bool voxel_ok(const BuildArgs& a, int32_t l, int32_t 
   return i >= 0 && j >= 0 && k >= 0 && i < (a.dims[0] << l) && j < (a.dims[1] << l) && k < (a.dims[2] << l);
 }
 
-__device__ bool hash_insert(const BuildArgs& a, uint64_t key) {
+// Slot of `key` (inserted if new), or -1 if the table is full.
+__device__ int64_t hash_insert(const BuildArgs& a, uint64_t key) {
   uint64_t h = mix64(key) & (uint64_t)(a.hcap - 1);
   for (int64_t probe = 0; probe < a.hcap; ++probe) {
     const uint64_t prev = atomicCAS((unsigned long long*)&a.hkeys[h], (unsigned long long)kNoKey,
                                     (unsigned long long)key);
-    if (prev == kNoKey || prev == key) return true;
+    if (prev == kNoKey || prev == key) return (int64_t)h;
     h = (h + 1) & (uint64_t)(a.hcap - 1);
   }
-  return false;
+  return -1;
 }
 
 __device__ int32_t hash_find(const BuildArgs& a, uint64_t key) {
@@ -104,21 +112,90 @@ __global__ void insert_kernel(BuildArgs a) {
   }
   for (int m = 0; m < l; ++m) {
     const int sh = l - m;
-    if (!hash_insert(a, node_key(m, q.y >> sh, q.z >> sh, q.w >> sh))) {
+    const int64_t slot = hash_insert(a, node_key(m, q.y >> sh, q.z >> sh, q.w >> sh));
+    if (slot < 0) {
       report(a.cnt, 4, (int32_t)v);
       return;
     }
+    atomicMin(&a.hvals[slot], (int32_t)v);
   }
+}
+
+// d0(v) <- l_v (no node yet), 0 for an invalid voxel
+__global__ void d0_init(BuildArgs a) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int4 q = reinterpret_cast<const int4*>(a.vox)[v];
+  a.d0[v] = voxel_ok(a, q.x, q.y, q.z, q.w) ? q.x : 0;
+}
+
+// d0(first voxel) <- min(depth) over the nodes
+__global__ void d0_min(BuildArgs a) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h >= a.hcap) return;
+  const uint64_t key = a.hkeys[h];
+  if (key == kNoKey) return;
+  const int32_t v = a.hvals[h];
+  if (v < 0 || v >= a.n) return;
+  atomicMin(&a.d0[v], (int32_t)(key >> 60));
+}
+
+// offs(v) <- number of nodes whose first voxel is v
+__global__ void node_counts(BuildArgs a) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int4 q = reinterpret_cast<const int4*>(a.vox)[v];
+  a.offs[v] = voxel_ok(a, q.x, q.y, q.z, q.w) ? q.x - a.d0[v] : 0;
 }
 
 __global__ void number_kernel(BuildArgs a) {
   const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= a.hcap) return;
-  if (a.hkeys[h] != kNoKey) {
-    const int32_t id = atomicAdd(&a.cnt->n_nodes, 1);
-    a.hvals[h] = (id < a.node_cap) ? id : -1;
-    if (id >= a.node_cap) report(a.cnt, 4, 0);
+  const uint64_t key = a.hkeys[h];
+  if (key == kNoKey) return;
+  const int32_t v = a.hvals[h];
+  int32_t id = -1;
+  if (v >= 0 && v < a.n) {
+    const int64_t i = (int64_t)a.offs[v] + (int32_t)(key >> 60) - a.d0[v];
+    if (i >= 0 && i < a.node_cap) id = (int32_t)i;
   }
+  a.hvals[h] = id;
+  if (id < 0) report(a.cnt, 4, 0);
+  atomicAdd(&a.cnt->n_nodes, 1);
+}
+
+// In-place exclusive prefix sum of int32 values, 2048 per block; sums[b] <- the block's total.
+constexpr int kScanThreads = 256, kScanItems = 8, kScanBlock = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void scan_blocks(int32_t* x, int64_t n, int32_t* sums) {
+  __shared__ int32_t part[kScanThreads];
+  const int64_t base = blockIdx.x * (int64_t)kScanBlock + threadIdx.x * kScanItems;
+  int32_t v[kScanItems], tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? x[base + i] : 0;
+    tot += v[i];
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan of the partials
+    const int32_t add = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t run = part[threadIdx.x] - tot;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) x[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = part[threadIdx.x];
+}
+
+__global__ void scan_add(int32_t* x, int64_t n, const int32_t* sums) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += sums[i / kScanBlock];
 }
 
 __device__ __forceinline__ bool claim(int32_t* slot, int32_t value) {
@@ -241,6 +318,21 @@ inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// int32 entries of block sums an exclusive scan of n values needs (all levels)
+int64_t scan_temp(int64_t n) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  return nb + (nb > 1 ? scan_temp(nb) : 0);
+}
+
+void launch_scan(int32_t* x, int64_t n, int32_t* tmp, hipStream_t stream) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  scan_blocks<<<(unsigned)nb, kScanThreads, 0, stream>>>(x, n, tmp);
+  if (nb > 1) {
+    launch_scan(tmp, nb, tmp + nb, stream);
+    scan_add<<<blocks_for(n, 256), 256, 0, stream>>>(x, n, tmp);
+  }
+}
+
 }  // namespace
 
 bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
@@ -278,6 +370,11 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   off = up(off + (size_t)hcap * 4);
   L->tmp_off = off;
   off = up(off + (size_t)n_root * 2);
+  L->order_off = 0;
+  if (K > 0 && n > 0) {  // node numbering: d0 [n], offsets [n], scan block sums
+    L->order_off = off;
+    off = up(off + (size_t)(2 * n + scan_temp(n)) * 4);
+  }
   L->counters_off = off;
   off = up(off + sizeof(BuildCounters));
   L->act_geo_off = L->act_rgb_off = L->act_int_off = 0;
@@ -329,15 +426,25 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   a.cnt = (BuildCounters*)(base + L.counters_off);
   a.box_tmp = (int32_t*)(base + L.box_tmp_off);
   a.nbox = (uint2*)(base + L.nbox_off);
+  a.d0 = L.order_off ? (int32_t*)(base + L.order_off) : nullptr;
+  a.offs = L.order_off ? a.d0 + n : nullptr;
   const int T = 256;
   fill_i32<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.root, kEmpty, L.n_root);
   if (L.node_cap > 0) box_init<<<blocks_for(L.node_cap, T) > 8192 ? 8192 : blocks_for(L.node_cap, T), T, 0, stream>>>(
       a.box_tmp, L.node_cap);
   if (L.node_cap > 0) fill_i32<<<blocks_for(L.node_cap * 8, T), T, 0, stream>>>(a.nodes, kEmpty, L.node_cap * 8);
   fill_u64<<<blocks_for(L.hash_cap, T), T, 0, stream>>>(a.hkeys, kNoKey, L.hash_cap);
+  fill_i32<<<blocks_for(L.hash_cap, T), T, 0, stream>>>(a.hvals, 0x7fffffff, L.hash_cap);
   init_counters<<<1, 64, 0, stream>>>(a.cnt);
   if (n > 0) insert_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
-  number_kernel<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
+  if (a.d0 != nullptr) {
+    const unsigned hb = (unsigned)((L.hash_cap + T - 1) / T);
+    d0_init<<<blocks_for(n, T), T, 0, stream>>>(a);
+    d0_min<<<hb, T, 0, stream>>>(a);
+    node_counts<<<blocks_for(n, T), T, 0, stream>>>(a);
+    launch_scan(a.offs, n, a.offs + n, stream);
+    number_kernel<<<hb, T, 0, stream>>>(a);
+  }
   if (n > 0) link_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
   box_pack<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
   {
