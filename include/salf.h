@@ -218,7 +218,7 @@ salf_status salf_generate_rays(salf_context* ctx, const salf_sensor* sensor, flo
 /* Explicit rays: device float [n, 3] origins and directions (unit length expected; depth is
  * measured in units of |d|).  All rays share [t_near, t_far].  image_width > 0 declares that the
  * rays form an image, row-major with that many rays per row (the last row may be short); the
- * renderer then gives each wave an 8x8 tile of them, exactly as for a sensor.  0 = no layout. */
+ * renderer then gives each wave an 8x8 tile of them, as for a camera.  0 = no layout. */
 typedef struct {
   const float* o;
   const float* d;
@@ -293,7 +293,7 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
 /* A server renders sensor requests (a scene and a sensor each) for many sensors and resident scenes
  * with continuous batching: a scheduler thread inside the library admits queued requests in
  * arrival order as soon as their outputs fit in the caller's HBM pool, and each scheduling cycle
- * launches one batched kernel over every 8x8 tile of all requests admitted since the previous
+ * launches one batched kernel over every 64-ray tile of all requests admitted since the previous
  * launch; waves pull tiles from a counter, so requests of uneven ray counts share the GPU.  Up
  * to `max_inflight` launches run at once on separate streams, so requests that arrive while
  * others are on the GPU start without waiting for them.  A request's rays render to the same bits

@@ -167,8 +167,7 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
     if (p->n > 0 && ((((uintptr_t)rays->o) & 3u) || (((uintptr_t)rays->d) & 3u)))
       return set_error(SALF_ERR_INVALID_ARG, "ray buffers must be 4-byte aligned");
   }
-  p->tiles_x = (p->img_w + 7) / 8;
-  p->tiles_y = (p->img_h + 7) / 8;
+  set_tiling(p, sensor ? sensor->model : -1);
   p->S = opts->samples_per_voxel;
   p->t_min = opts->t_min;
   for (int c = 0; c < 3; ++c) p->bg[c] = opts->background[c];

@@ -58,10 +58,21 @@ struct RenderParams {
   float t_min;
   float bg[3];
   salf_outputs out;
-  int32_t tiled;             // 1: waves take 8x8 tiles of an img_w x img_h ray image
+  int32_t tiled;             // 1: waves take tiles of 64 rays of an img_w x img_h ray image
   int32_t img_w, img_h;
   int32_t tiles_x, tiles_y;
+  int32_t tw_log2;           // tile width 2^tw_log2, height 64 >> tw_log2
 };
+
+// Tile shape of a wave: 8 x 8 pixels for cameras (and explicit rays with an image layout), 32
+// columns x 2 beams for a spinning LiDAR, whose neighbouring beams differ far more in path length
+// than neighbouring columns do.
+inline void set_tiling(RenderParams* p, int sensor_model) {
+  p->tw_log2 = sensor_model == SALF_LIDAR_SPINNING ? 5 : 3;
+  const int tw = 1 << p->tw_log2, th = 64 >> p->tw_log2;
+  p->tiles_x = (p->img_w + tw - 1) / tw;
+  p->tiles_y = (p->img_h + th - 1) / th;
+}
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream);
 

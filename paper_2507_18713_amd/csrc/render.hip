@@ -2,9 +2,9 @@
 // samples of each voxel's local field per segment, and alpha compositing of colour, depth,
 // intensity and opacity with FP32 transmittance and early termination (Eq. 1-4, Sec. 3.2).
 //
-// Work mapping: one lane per ray.  In sensor mode a wave64 covers an 8x8 tile of pixels (or of
-// LiDAR beams x columns) so that the lanes of a wave walk nearby voxels and share their parameter
-// cache lines; ray generation is fused (no ray buffer in HBM).
+// Work mapping: one lane per ray.  In sensor mode a wave64 covers a tile of 64 neighbouring rays
+// (8x8 pixels; 32 columns x 2 beams of a LiDAR) so that the lanes of a wave walk nearby voxels and
+// share their parameter cache lines; ray generation is fused (no ray buffer in HBM).
 #include "internal.hpp"
 
 namespace salf {
@@ -114,15 +114,15 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
   return !(acc.T < t_min);
 }
 
-// The ray of this lane of wave `wave` (tiled: the wave's 8x8 tile; else 64 consecutive rays): its
+// The ray of this lane of wave `wave` (tiled: the wave's tile; else 64 consecutive rays): its
 // index and grid frame.  Returns false for lanes without a ray.
 __device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, int64_t& ray, float d[3], RayFrame& f) {
   const int lane = threadIdx.x & 63;
   int col = 0, row = 0;
   if (p.tiled) {
     const int tx = (int)(wave % p.tiles_x), ty = (int)(wave / p.tiles_x);
-    col = tx * 8 + (lane & 7);
-    row = ty * 8 + (lane >> 3);
+    col = tx * (1 << p.tw_log2) + (lane & ((1 << p.tw_log2) - 1));
+    row = ty * (64 >> p.tw_log2) + (lane >> p.tw_log2);
     if (ty >= p.tiles_y || col >= p.img_w || row >= p.img_h) return false;
     ray = (int64_t)row * p.img_w + col;
     if (ray >= p.n) return false;

@@ -337,8 +337,7 @@ salf_status salf_server_submit(salf_server* server, int32_t scene_id, const salf
   r.p.tiled = 1;
   r.p.img_w = sensor->width;
   r.p.img_h = sensor->height;
-  r.p.tiles_x = (sensor->width + 7) / 8;
-  r.p.tiles_y = (sensor->height + 7) / 8;
+  set_tiling(&r.p, sensor->model);
   r.p.n = n;
   r.p.S = opts->samples_per_voxel;
   r.p.t_min = opts->t_min;

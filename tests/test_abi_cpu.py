@@ -5,6 +5,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 import tempfile
 
 import numpy as np
@@ -155,3 +156,10 @@ def test_null_arguments_are_rejected(L):
     assert lib.salf_sync(None, None) == -1
     assert lib.salf_render(None, 0, None, None, None, None, None) == -1
     assert lib.salf_scene_get_stats(None, 0, None) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2, r.stderr
+    assert "one GPU" in r.stderr
