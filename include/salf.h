@@ -233,7 +233,18 @@ typedef struct {
   float t_min;               /* a ray stops after the voxel that leaves T < t_min; 0 = never stop */
   float background[3];       /* added as T_end * background to the colour                           */
   int32_t reserved;          /* must be 0                                                            */
+  void* d_work;              /* optional device scratch for the tile schedule (salf_render_work_size) */
+  size_t work_bytes;         /* its size; ignored when d_work is NULL                               */
 } salf_render_opts;
+
+/* Device bytes of the optional tile-schedule buffer (salf_render_opts.d_work) of a render of
+ * `sensor` or of explicit `rays` (exactly one non-NULL).  With the buffer, salf_render and
+ * salf_render_backward first estimate the cost of every 64-ray tile by walking its centre ray
+ * through the root grid (for each occupied root cell, the length of the ray inside the bounds of
+ * the cell's voxels divided by the size of its finest voxels, about the voxels it crosses), then
+ * process the tiles heaviest first, which shortens the tail of the launch.  Outputs are the same
+ * bits in any order.  Calls that may overlap must not share a buffer.  Errors: INVALID_ARG. */
+salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* rays, size_t* bytes);
 
 /* Per-ray outputs, device FP32 unless noted; a NULL pointer means "not wanted".
  *   rgb [n, 3]    C = sum w rgb + T_end * background   (Eq. 3)

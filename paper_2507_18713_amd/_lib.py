@@ -44,7 +44,7 @@ class Rays(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("samples_per_voxel", C.c_int32), ("t_min", C.c_float), ("background", C.c_float * 3),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("d_work", C.c_void_p), ("work_bytes", C.c_size_t)]
 
 
 class Outputs(C.Structure):
@@ -87,6 +87,7 @@ SIGNATURES = {
                                        C.c_void_p, C.c_void_p]),
     "salf_render": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(RenderOpts),
                                 C.POINTER(Outputs), C.c_void_p]),
+    "salf_render_work_size": (C.c_int32, [C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(C.c_size_t)]),
     "salf_trace_hits": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Rays), C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "salf_render_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),

@@ -177,13 +177,24 @@ def generate_rays(sensor: dict, device="cuda") -> Dict[str, torch.Tensor]:
     return {"o": o, "d": d, "t": t, "valid": v}
 
 
-def _opts(samples, t_min, background) -> _lib.RenderOpts:
+def _opts(samples, t_min, background, work: Optional[torch.Tensor] = None) -> _lib.RenderOpts:
     op = _lib.RenderOpts()
     op.samples_per_voxel = int(samples)
     op.t_min = float(t_min)
     op.background[:] = [float(x) for x in background]
     op.reserved = 0
+    op.d_work = work.data_ptr() if work is not None else None
+    op.work_bytes = work.numel() if work is not None else 0
     return op
+
+
+def _schedule_work(sen, rays, dev) -> torch.Tensor:
+    """Scratch for the heaviest-tiles-first schedule of one launch (from torch's stream-ordered
+    allocator, so launches on other streams never share it)."""
+    n = C.c_size_t()
+    call("salf_render_work_size", C.byref(sen) if sen is not None else None,
+         C.byref(rays) if rays is not None else None, C.byref(n))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=dev)
 
 
 def _rays_struct(o, d, t_near, t_far, device, image_width=0):
@@ -205,9 +216,11 @@ def _rays_struct(o, d, t_near, t_far, device, image_width=0):
 def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor] = None,
            d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
            outputs: Iterable[str] = ("rgb", "depth", "opacity"), t_near: float = 0.0, t_far: float = math.inf,
-           out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0) -> Dict[str, torch.Tensor]:
+           out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0,
+           schedule: bool = True) -> Dict[str, torch.Tensor]:
     """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
     image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
+    schedule: process the launch's tiles heaviest first (same outputs, shorter tail).
     Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
     n_hits int32 [n])."""
     dev = scene.device
@@ -230,9 +243,10 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     ob = _lib.Outputs()
     for k in OUTPUT_NAMES:
         setattr(ob, k, res[k].data_ptr() if k in res else None)
+    work = _schedule_work(sen, rays, dev) if schedule else None
     call("salf_render", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(ob),
-         _stream(dev))
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work)),
+         C.byref(ob), _stream(dev))
     return res
 
 
@@ -255,7 +269,7 @@ def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_
 def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[str, Optional[torch.Tensor]],
                     sensor: Optional[dict] = None, o=None, d=None, samples: int = 4, t_min: float = 1e-6,
                     background=(0.0, 0.0, 0.0), t_near: float = 0.0, t_far: float = math.inf,
-                    d_geo=None, d_rgb=None, d_int=None, image_width: int = 0):
+                    d_geo=None, d_rgb=None, d_int=None, image_width: int = 0, schedule: bool = True):
     """Accumulate dL/d(params) of a corner-field render into d_geo/d_rgb/d_int (allocated zeroed if
     None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
     dev = scene.device
@@ -281,8 +295,9 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
             t = t.contiguous()
             grads[k] = t
         setattr(g, f, t.data_ptr() if t is not None else None)
+    work = _schedule_work(sen, rays, dev) if schedule else None
     call("salf_render_backward", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(sv),
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work)), C.byref(sv),
          C.byref(g), _ptr(d_geo), _ptr(d_rgb), _ptr(d_int), _stream(dev))
     return d_geo, d_rgb, d_int
 

@@ -133,17 +133,11 @@ salf_status find_scene(salf_context* ctx, int32_t id, Scene** out) {
   return SALF_OK;
 }
 
-// Fill the parts of RenderParams shared by render and backward.
-salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
-                           const salf_render_opts* opts, RenderParams* p, int* field) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
-  if (st) return st;
+// The rays of a launch (sensor or explicit rays) and their tiling.
+salf_status ray_layout(const salf_sensor* sensor, const salf_rays* rays, RenderParams* p) {
+  salf_status st;
   if ((sensor == nullptr) == (rays == nullptr))
     return set_error(SALF_ERR_INVALID_ARG, "pass exactly one of sensor and rays");
-  if ((st = validate_opts(opts))) return st;
-  memset(p, 0, sizeof(*p));
-  p->scene = sc->view;
   if (sensor) {
     if ((st = validate_sensor(sensor))) return st;
     p->sensor = *sensor;
@@ -168,6 +162,26 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
       return set_error(SALF_ERR_INVALID_ARG, "ray buffers must be 4-byte aligned");
   }
   set_tiling(p, sensor ? sensor->model : -1);
+  return SALF_OK;
+}
+
+// Fill the parts of RenderParams shared by render and backward.
+salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
+                           const salf_render_opts* opts, RenderParams* p, int* field) {
+  Scene* sc = nullptr;
+  salf_status st = find_scene(ctx, scene_id, &sc);
+  if (st) return st;
+  if ((st = validate_opts(opts))) return st;
+  memset(p, 0, sizeof(*p));
+  if ((st = ray_layout(sensor, rays, p))) return st;
+  p->scene = sc->view;
+  if (opts->d_work) {
+    const size_t need = tile_work_bytes(tile_count(*p));
+    if (opts->work_bytes < need)
+      return set_error(SALF_ERR_INVALID_ARG, "work buffer holds %zu bytes; the tile schedule needs %zu",
+                       opts->work_bytes, need);
+    if ((uintptr_t)opts->d_work & 255u) return set_error(SALF_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
+  }
   p->S = opts->samples_per_voxel;
   p->t_min = opts->t_min;
   for (int c = 0; c < 3; ++c) p->bg[c] = opts->background[c];
@@ -265,6 +279,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.nodes = (const int32_t*)((char*)d_workspace + L.nodes_off);
   v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
   v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
+  v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
   v.act_geo = v.act_rgb = v.act_int = nullptr;
   if (desc->flags & SALF_SCENE_PREACTIVATE) {
     v.act_geo = (const float*)((char*)d_workspace + L.act_geo_off);
@@ -362,7 +377,18 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
     return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
   p.out = *out;
   DeviceGuard g(ctx->device);
+  if ((st = check_hip(launch_tile_order(p, opts->d_work, (hipStream_t)stream), "tile schedule launch"))) return st;
   return check_hip(launch_render(p, field, (hipStream_t)stream), "render launch");
+}
+
+salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* rays, size_t* bytes) {
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  RenderParams p;
+  memset(&p, 0, sizeof(p));
+  const salf_status st = ray_layout(sensor, rays, &p);
+  if (st) return st;
+  *bytes = tile_work_bytes(tile_count(p));
+  return SALF_OK;
 }
 
 salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
@@ -403,6 +429,7 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
   b.drgb = d_drgb;
   b.dint = d_dint;
   DeviceGuard g(ctx->device);
+  if ((st = check_hip(launch_tile_order(b.fwd, opts->d_work, (hipStream_t)stream), "tile schedule launch"))) return st;
   return check_hip(launch_backward(b, (hipStream_t)stream), "backward launch");
 }
 

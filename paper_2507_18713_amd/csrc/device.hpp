@@ -34,6 +34,7 @@ struct SceneView {
   const float* inten;    // [N][8] or null
   const uint8_t* skip;   // [Dz][Dy][Dx] Chebyshev distance (in root cells, capped) to the nearest
                          // occupied root cell; 0 = occupied.  Null: no empty-space skipping.
+  const int32_t* lmax;   // [Dz][Dy][Dx] finest voxel level in each root cell (tile cost estimates)
   const float* act_geo;  // activated corner values (pre-activated corner scenes), same layouts as
   const float* act_rgb;  // geo / rgb / inten; null otherwise
   const float* act_int;
@@ -387,6 +388,54 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
   }
 }
 
+
+// Estimated number of voxels a ray crosses, from the root grid alone (used to schedule tiles):
+// for every occupied root cell on the ray, the length inside the bounds of the cell's voxels
+// times 2^(finest level in the cell) / root-cell size, plus a quarter per root cell visited.
+__device__ inline float root_cost(const SceneView& s, const RayFrame& f) {
+  if (!f.valid) return 0.0f;
+  const int K = s.K;
+  float t, t_exit;
+  {
+    const int32_t glo[3] = {0, 0, 0};
+    const int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
+    if (!box_interval(f, glo, ghi, t, t_exit) || !(t < t_exit)) return 0.0f;
+  }
+  RootAxis ax, ay, az;
+  root_axis_init<0>(f, s, t, ax);
+  root_axis_init<1>(f, s, t, ay);
+  root_axis_init<2>(f, s, t, az);
+  float len = 0.0f;
+  int steps = 0;
+  while (steps < (1 << 16)) {
+    ++steps;
+    const float cell_exit = fminf(fminf(ax.nxt, ay.nxt), fminf(az.nxt, t_exit));
+    const int64_t lin = ((int64_t)az.k * s.dims[1] + ay.k) * s.dims[0] + ax.k;
+    const int32_t code = s.root[lin];
+    float t_next = cell_exit;
+    if (code >= 0) {
+      const int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
+      float b_in, b_out;
+      if (node_bounds(f, lo, s.nbox[code], b_in, b_out)) {
+        const float l = fminf(b_out, cell_exit) - fmaxf(b_in, t);
+        if (l > 0.0f) len += l * (float)(1 << s.lmax[lin]);
+      }
+    } else if (is_leaf_code(code)) {
+      len += cell_exit - t;
+    } else if (s.skip != nullptr) {
+      const int d = s.skip[lin];
+      if (d > 1)
+        t_next = fminf(fminf(cube_exit<0>(f, s, ax, d), cube_exit<1>(f, s, ay, d)),
+                       fminf(cube_exit<2>(f, s, az, d), t_exit));
+    }
+    if (!(t_next < t_exit)) break;
+    t = t_next;
+    if (!root_axis_advance<0>(f, s, t, ax) || !root_axis_advance<1>(f, s, t, ay) ||
+        !root_axis_advance<2>(f, s, t, az))
+      break;
+  }
+  return len * s.gs32 / (float)(1 << K) + 0.25f * (float)steps;
+}
 
 // ----------------------------------------------------------------------------- sensors
 __device__ inline void rotate_rodrigues(const float w[3], float dt, float v[3]) {

@@ -116,8 +116,8 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
 
 // The ray of this lane of wave `wave` (tiled: the wave's tile; else 64 consecutive rays): its
 // index and grid frame.  Returns false for lanes without a ray.
-__device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, int64_t& ray, float d[3], RayFrame& f) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, int lane, int64_t& ray, float d[3],
+                                         RayFrame& f) {
   int col = 0, row = 0;
   if (p.tiled) {
     const int tx = (int)(wave % p.tiles_x), ty = (int)(wave / p.tiles_x);
@@ -150,6 +150,11 @@ __device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, in
   return true;
 }
 
+// Tile rendered by wave w of a launch: the schedule's entry when there is one.
+__device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t w) {
+  return (p.order != nullptr && w < tile_count(p)) ? (int64_t)p.order[w] : w;
+}
+
 // Render the rays of one wave (tile `wave` of p) and store their outputs.  stk: this lane's node
 // stack (stride kThreads).  Shared by the single-request kernel and the batched kernel, so a ray
 // renders to the same bits alone or in a batch.
@@ -158,7 +163,7 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   int64_t ray;
   float d[3];
   RayFrame f;
-  if (!lane_ray(p, wave, ray, d, f)) return;
+  if (!lane_ray(p, wave, threadIdx.x & 63, ray, d, f)) return;
   float sh[4] = {kShC0, kShC1 * d[0], kShC1 * d[1], kShC1 * d[2]};
   Accum acc;
   acc.T = 1.0f;
@@ -186,7 +191,69 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
 template <int FIELD, bool RGB, bool INT>
 __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
-  render_wave<FIELD, RGB, INT>(p, (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6, stk + threadIdx.x);
+  const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  render_wave<FIELD, RGB, INT>(p, scheduled_tile(p, w), stk + threadIdx.x);
+}
+
+// ----------------------------------------------------------------------------- tile schedule
+// Heaviest tiles first (longest-processing-time-first list scheduling): a tile's cost is the sum
+// of the root-grid estimates of four probe rays (at the quarter points of the tile), quantized to
+// kCostBuckets logarithmic buckets; a counting sort over the buckets writes the order.  Ties are
+// placed in arbitrary order, which changes the schedule only, never a ray's result.  A launch
+// whose tiles all fit on the GPU at once keeps its own order (sorting would only crowd the heavy
+// tiles onto the same compute units).
+constexpr int kCostBuckets = 256;
+
+__global__ void clear_u32(uint32_t* x, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0u;
+}
+
+// Four lanes per tile, one probe each; the tile's cost is their sum.
+__global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, int64_t n_tiles, uint32_t* key,
+                                                             uint32_t* hist) {
+  const int64_t tile = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 2;
+  const int probe = threadIdx.x & 3;
+  const int tw = p.tiled ? 1 << p.tw_log2 : 64, th = p.tiled ? 64 >> p.tw_log2 : 1;
+  const int lane = ((probe >> 1) ? (3 * th) / 4 : th / 4) * tw + ((probe & 1) ? (3 * tw) / 4 : tw / 4);
+  float cost = 0.0f;
+  if (tile < n_tiles) {
+    int64_t ray;
+    float d[3];
+    RayFrame f;
+    if (lane_ray(p, tile, lane, ray, d, f) || lane_ray(p, tile, 0, ray, d, f)) cost = root_cost(p.scene, f);
+  }
+  cost += __shfl_xor(cost, 1);
+  cost += __shfl_xor(cost, 2);
+  if (tile >= n_tiles || probe != 0) return;
+  const int b = (int)(__log2f(1.0f + cost) * 16.0f);
+  const uint32_t bucket = (uint32_t)(b < 0 ? 0 : (b >= kCostBuckets ? kCostBuckets - 1 : b));
+  key[tile] = bucket;
+  atomicAdd(&hist[bucket], 1u);
+}
+
+__global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint32_t* key, int64_t n_tiles,
+                                                              const uint32_t* hist, uint32_t* cursor, int32_t* order) {
+  static_assert(kThreads == kCostBuckets, "one thread per bucket");
+  __shared__ uint32_t above[kCostBuckets];
+  // above[b] = tiles in buckets heavier than b: an exclusive scan from the heaviest bucket down
+  const int t = threadIdx.x;
+  const uint32_t own = hist[kCostBuckets - 1 - t];
+  above[t] = own;
+  __syncthreads();
+  for (int off = 1; off < kCostBuckets; off <<= 1) {
+    const uint32_t add = t >= off ? above[t - off] : 0u;
+    __syncthreads();
+    above[t] += add;
+    __syncthreads();
+  }
+  const uint32_t excl = above[t] - own;
+  __syncthreads();
+  above[kCostBuckets - 1 - t] = excl;
+  __syncthreads();
+  const int64_t tile = blockIdx.x * (int64_t)kThreads + t;
+  if (tile >= n_tiles) return;
+  const uint32_t b = key[tile];
+  order[above[b] + atomicAdd(&cursor[b], 1u)] = (int32_t)tile;
 }
 
 // Batched render of several requests in one launch: a grid sized to the GPU's resident capacity
@@ -282,7 +349,8 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   int64_t ray;
   float dir[3];
   RayFrame f;
-  if (!lane_ray(p, (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6, ray, dir, f)) return;
+  const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  if (!lane_ray(p, scheduled_tile(p, w), threadIdx.x & 63, ray, dir, f)) return;
   const int32_t n_stop = p.out.n_hits[ray];
   if (n_stop <= 0) return;
   const float T_end = p.out.t_end[ray];
@@ -423,6 +491,44 @@ hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stre
 }
 
 }  // namespace
+
+namespace {
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t tile_work_bytes(int64_t n_tiles) {
+  return 2 * align256((size_t)n_tiles * 4) + 2 * kCostBuckets * sizeof(uint32_t);
+}
+
+hipError_t launch_tile_order(RenderParams& p, void* work, hipStream_t stream) {
+  p.order = nullptr;
+  const int64_t n_tiles = tile_count(p);
+  if (work == nullptr || n_tiles <= 1) return hipSuccess;
+  // waves the GPU holds at once: 4 SIMDs per compute unit, 4 waves each at the render kernels'
+  // register use
+  static int resident[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64 && resident[dev] == 0) {
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    resident[dev] = 16 * (cus > 0 ? cus : 1);
+  }
+  if (dev >= 0 && dev < 64 && n_tiles <= resident[dev]) return hipSuccess;
+  char* w = (char*)work;
+  uint32_t* key = (uint32_t*)w;
+  int32_t* order = (int32_t*)(w + align256((size_t)n_tiles * 4));
+  uint32_t* hist = (uint32_t*)(w + 2 * align256((size_t)n_tiles * 4));
+  uint32_t* cursor = hist + kCostBuckets;
+  const unsigned blocks = (unsigned)((n_tiles + kThreads - 1) / kThreads);
+  clear_u32<<<1, 256, 0, stream>>>(hist, 2 * kCostBuckets);
+  tile_cost_kernel<<<(unsigned)((4 * n_tiles + kThreads - 1) / kThreads), kThreads, 0, stream>>>(p, n_tiles, key, hist);
+  tile_order_kernel<<<blocks, kThreads, 0, stream>>>(key, n_tiles, hist, cursor, order);
+  e = hipGetLastError();
+  if (e == hipSuccess) p.order = order;
+  return e;
+}
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
   const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;

@@ -62,6 +62,7 @@ struct BuildArgs {
   int64_t hcap;
   int64_t node_cap;
   BuildCounters* cnt;
+  int32_t* lmax;     // [n_root] finest voxel level in each root cell (0 if empty)
   int32_t* box_tmp;  // [node_cap][6] absolute finest bounds of each node's voxels (min lo, max hi)
   uint2* nbox;       // [node_cap] packed bounds relative to the node
   int32_t* d0;       // [n] shallowest depth of a node whose first voxel is v (numbering only)
@@ -225,7 +226,9 @@ __global__ void link_kernel(BuildArgs a) {
     }
     int32_t* slot;
     if (m == 0) {
-      slot = &a.root[((int64_t)z * a.dims[1] + y) * a.dims[0] + x];
+      const int64_t cell = ((int64_t)z * a.dims[1] + y) * a.dims[0] + x;
+      slot = &a.root[cell];
+      atomicMax(&a.lmax[cell], l);
     } else {
       slot = &a.nodes[(int64_t)parent * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2))];
     }
@@ -358,6 +361,8 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   off = up(off + (size_t)n_root * 4);
   L->skip_off = off;
   off = up(off + (size_t)n_root);
+  L->lmax_off = off;
+  off = up(off + (size_t)n_root * 4);
   L->nodes_off = off;
   off = up(off + (size_t)node_cap * 32);
   L->nbox_off = off;
@@ -425,11 +430,13 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   a.node_cap = L.node_cap;
   a.cnt = (BuildCounters*)(base + L.counters_off);
   a.box_tmp = (int32_t*)(base + L.box_tmp_off);
+  a.lmax = (int32_t*)(base + L.lmax_off);
   a.nbox = (uint2*)(base + L.nbox_off);
   a.d0 = L.order_off ? (int32_t*)(base + L.order_off) : nullptr;
   a.offs = L.order_off ? a.d0 + n : nullptr;
   const int T = 256;
   fill_i32<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.root, kEmpty, L.n_root);
+  fill_i32<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.lmax, 0, L.n_root);
   if (L.node_cap > 0) box_init<<<blocks_for(L.node_cap, T) > 8192 ? 8192 : blocks_for(L.node_cap, T), T, 0, stream>>>(
       a.box_tmp, L.node_cap);
   if (L.node_cap > 0) fill_i32<<<blocks_for(L.node_cap * 8, T), T, 0, stream>>>(a.nodes, kEmpty, L.node_cap * 8);

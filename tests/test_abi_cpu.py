@@ -47,7 +47,7 @@ int main(void) {
   printf("SceneStats %zu %zu\n", sizeof(salf_scene_stats), offsetof(salf_scene_stats, workspace_bytes));
   printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
   printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
-  printf("RenderOpts %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, reserved));
+  printf("RenderOpts %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, reserved), offsetof(salf_render_opts, work_bytes));
   printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
   printf("ServerOpts %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight));
@@ -68,7 +68,7 @@ int main(void) {
         "SceneStats": [C.sizeof(S.SceneStats), S.SceneStats.workspace_bytes.offset],
         "Sensor": [C.sizeof(S.Sensor), S.Sensor.R0.offset, S.Sensor.t_far.offset],
         "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
-        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.reserved.offset],
+        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.reserved.offset, S.RenderOpts.work_bytes.offset],
         "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
         "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset],
@@ -95,10 +95,11 @@ def test_workspace_size_host_logic(L):
     small = n.value
     assert lib.salf_scene_workspace_size(C.byref(_desc(L)), 10000, C.byref(n)) == 0
     assert n.value > small
-    # a K = 0 scene needs no nodes: the root grid (4 B per cell), the skip-distance grid and its two
-    # build-time temporaries (1 B per cell each), a minimal hash table and the counters
+    # a K = 0 scene needs no nodes: the root grid and the finest-level grid (4 B per cell each),
+    # the skip-distance grid and its two build-time temporaries (1 B per cell each), a minimal
+    # hash table and the counters
     assert lib.salf_scene_workspace_size(C.byref(_desc(L, dims=(32, 32, 32), K=0)), 4096, C.byref(n)) == 0
-    assert 32 ** 3 * 7 <= n.value < 32 ** 3 * 7 + 64 * 1024
+    assert 32 ** 3 * 11 <= n.value < 32 ** 3 * 11 + 64 * 1024
     # invalid descriptions
     for bad in (_desc(L, K=9), _desc(L, s0=0.0), _desc(L, s0=math.nan), _desc(L, dims=(0, 4, 4)),
                 _desc(L, dims=(1 << 17, 4, 4), K=4), _desc(L, field=7)):
@@ -123,6 +124,27 @@ def test_sensor_ray_count_host_logic(L):
     assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
     bad = dict(synth.config1_camera(), t_near=2.0, t_far=1.0)
     assert lib.salf_sensor_ray_count(C.byref(sensor_struct(bad)), C.byref(n)) == -1
+
+
+def test_render_work_size_host_logic(L):
+    from paper_2507_18713_amd.api import sensor_struct
+    import synth
+    lib = L.lib()
+    n = C.c_size_t()
+    up = lambda x: (x + 255) // 256 * 256
+    # camera: 8x8 tiles; LiDAR: 32 columns x 2 beams; explicit rays: groups of 64 (or 8x8 tiles of
+    # an image layout); per tile a cost key and an order entry, plus two 256-entry histograms
+    for s, tiles in ((synth.config1_camera(), 240 * 135), (synth.config2_lidar(), 64 * 32)):
+        assert lib.salf_render_work_size(C.byref(sensor_struct(s)), None, C.byref(n)) == 0
+        assert n.value == 2 * up(tiles * 4) + 2048
+    r = L.Rays()
+    r.o, r.d = 256, 512  # never dereferenced by a size query
+    r.n, r.t_near, r.t_far, r.image_width = 1000, 0.0, math.inf, 0
+    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 2 * up(16 * 4) + 2048
+    r.image_width = 50  # 50 x 20 image: 7 x 3 tiles
+    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 2 * up(21 * 4) + 2048
+    assert lib.salf_render_work_size(None, None, C.byref(n)) == -1
+    assert lib.salf_render_work_size(C.byref(sensor_struct(synth.config1_camera())), C.byref(r), C.byref(n)) == -1
 
 
 def test_server_sizes_host_logic(L):

@@ -109,3 +109,21 @@ def test_forward_is_deterministic(salf, c1):
     b = salf.render(scene, sensor=cam, outputs=("rgb", "depth", "opacity", "n_hits"))
     for k in a:
         assert torch.equal(a[k], b[k])
+
+
+def test_tile_schedule_changes_nothing_but_the_order(salf, c1):
+    """Heaviest-tiles-first scheduling (the default) renders every ray to the same bits as the
+    launch in tile order: the camera frame, a LiDAR sweep large enough to be scheduled (128 x 4,096
+    rays; launches that fit on the GPU at once keep their order) and explicit rays."""
+    data, ps, scene = c1
+    big_lidar = synth.lidar_spinning(128, 4096, -25.0, 15.0, np.eye(3), (-60.0, 0.37, 1.85), 0.1, v=(10, 0, 0))
+    for sensor, outs in ((synth.config1_camera(), ("rgb", "depth", "opacity", "t_end", "n_hits")),
+                         (big_lidar, ("depth", "opacity", "t_end", "n_hits"))):
+        a = salf.render(scene, sensor=sensor, outputs=outs, schedule=True)
+        b = salf.render(scene, sensor=sensor, outputs=outs, schedule=False)
+        for k in outs:
+            assert torch.equal(a[k], b[k]), (sensor["model"], k)
+    rays = salf.generate_rays(synth.config1_camera(), dev())
+    a = salf.render(scene, o=rays["o"], d=rays["d"], outputs=("rgb", "n_hits"), schedule=True)
+    b = salf.render(scene, o=rays["o"], d=rays["d"], outputs=("rgb", "n_hits"), schedule=False)
+    assert torch.equal(a["rgb"], b["rgb"]) and torch.equal(a["n_hits"], b["n_hits"])
