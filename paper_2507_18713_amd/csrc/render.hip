@@ -372,6 +372,14 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const double rS = 1.0 / S;
   float T = 1.0f, PC[3] = {0.0f, 0.0f, 0.0f}, PD = 0.0f, PI = 0.0f;
   int32_t count = 0;
+  // per-wave gradient rows in LDS, [row][lane] with a stride of 65 so that the lanes summing
+  // different rows of one lane's column hit different banks
+  constexpr int kIntRow = RGB ? 32 : 8;
+  constexpr int kRows = kIntRow + (INT ? 8 : 0);
+  constexpr int kRedStride = 65;
+  __shared__ float red_all[(kThreads / 64) * kRows * kRedStride];
+  float* red = red_all + (threadIdx.x >> 6) * (kRows * kRedStride);
+  const int lane = threadIdx.x & 63;
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
@@ -461,20 +469,44 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       }
       T = Tn;
     }
-    if (b.dgeo) {
+    // this lane's gradient row for the voxel (activation derivative applied): 8 density corners,
+    // then 24 colour and 8 intensity corners when present
 #pragma unroll
-      for (int i = 0; i < 8; ++i) unsafeAtomicAdd(&b.dgeo[(int64_t)v * 8 + i], ag[i] * sigmoid_f(zg[i]));
-    }
-    if (RGB && b.drgb) {
+    for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * sigmoid_f(zg[i]);
+    if (RGB) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          unsafeAtomicAdd(&b.drgb[(int64_t)v * 24 + ch * 8 + i], ar[ch][i] * cr[ch][i] * (1.0f - cr[ch][i]));
+          red[(8 + ch * 8 + i) * kRedStride + lane] = ar[ch][i] * cr[ch][i] * (1.0f - cr[ch][i]);
     }
-    if (INT && b.dint) {
+    if (INT) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) unsafeAtomicAdd(&b.dint[(int64_t)v * 8 + i], ai[i] * ci[i] * (1.0f - ci[i]));
+      for (int i = 0; i < 8; ++i) red[(kIntRow + i) * kRedStride + lane] = ai[i] * ci[i] * (1.0f - ci[i]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Lanes that hit the same voxel at this point form a group; its members split the rows among
+    // themselves, add the group's entries of each row in lane order and issue one atomic per value,
+    // instead of one atomic per value and lane on the same addresses.
+    uint64_t pending = __ballot(1), mine = 0;
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int32_t vl = __shfl(v, leader);
+      const uint64_t m = __ballot(v == vl) & pending;
+      if (v == vl) mine = m;
+      pending &= ~m;
+    }
+    const int size = __popcll(mine);
+    const int rank = __popcll(mine & ((1ull << lane) - 1ull));
+    for (int j = rank; j < kRows; j += size) {
+      float sum = 0.0f;
+      for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
+      float* dst = j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
+                         : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)v * 24 + (j - 8) : nullptr)
+                                          : (b.dint ? b.dint + (int64_t)v * 8 + (j - kIntRow) : nullptr));
+      if (dst) unsafeAtomicAdd(dst, sum);
     }
     return ++count < n_stop;
   });
