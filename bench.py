@@ -390,28 +390,35 @@ def main():
 
     def step(ev=None):
         # the LiDAR sweep of a step runs on a second stream beside its camera frame; a step
-        # starts once the previous step's two renders have finished.  ev: events recorded around
-        # the camera render (main stream) and the LiDAR render (second stream)
+        # starts once the previous step's two renders have finished.  Every step builds the camera
+        # frame's tile schedule (a frame's pose may change) and renders with it.  ev: events
+        # around the schedule and the camera render (main stream) and the LiDAR render (second
+        # stream)
         side_stream.wait_stream(main_stream)
         if ev is not None:
             ev[0].record(main_stream)
-        salf.render(scene, sensor=cam, outputs=cam_out.keys(), out=cam_out, **opts)
+        sched = salf.render_schedule(scene, sensor=cam)
         if ev is not None:
             ev[1].record(main_stream)
+        salf.render(scene, sensor=cam, outputs=cam_out.keys(), out=cam_out, schedule=sched, **opts)
+        if ev is not None:
+            ev[2].record(main_stream)
         with torch.cuda.stream(side_stream):
             if ev is not None:
-                ev[2].record(side_stream)
+                ev[3].record(side_stream)
             salf.render(scene, sensor=lid, outputs=lid_out.keys(), out=lid_out, **opts)
             if ev is not None:
-                ev[3].record(side_stream)
+                ev[4].record(side_stream)
         main_stream.wait_stream(side_stream)
 
     def kernel_ms(sensor, outs):
-        """Average duration of one render alone, by HIP events on the stream it runs on."""
+        """Average duration of one render alone (its schedule built beforehand), by HIP events on
+        the stream it runs on."""
+        sched = salf.render_schedule(scene, sensor=sensor)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(args.steps):
-            salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, **opts)
+            salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, schedule=sched, **opts)
         ev1.record()
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / args.steps
@@ -424,15 +431,16 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     t_start = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     # per-launch durations inside the timed region (each render shares the GPU with the other)
-    cam_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    lid_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    sched_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    cam_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    lid_ms = sum(e[3].elapsed_time(e[4]) for e in evs) / args.steps
     # steady-state period: camera start to camera start (steps are serialized by the stream waits)
     step_ms = evs[0][0].elapsed_time(evs[-1][0]) / (args.steps - 1) if args.steps > 1 else None
     rays = n_cam + n_lid
@@ -479,6 +487,7 @@ def main():
         },
         "camera": {"ms": round(cam_ms, 4), "mrays_s": round(n_cam / cam_ms / 1e3, 2),
                    "ms_alone": None if cam_alone_ms is None else round(cam_alone_ms, 4),
+                   "schedule_ms": round(sched_ms, 4),
                    "ms_raw_logit_scene": round(cam_raw_ms, 4),
                    "shaded_hits_per_ray": round(hits_cam / n_cam, 3), "algorithmic_bytes": cam_bytes},
         "lidar": {"ms": round(lid_ms, 4), "mrays_s": round(n_lid / lid_ms / 1e3, 2),

@@ -232,19 +232,33 @@ typedef struct {
   int32_t samples_per_voxel; /* S in [1, SALF_MAX_SAMPLES]; the workloads use 4, the paper 1        */
   float t_min;               /* a ray stops after the voxel that leaves T < t_min; 0 = never stop */
   float background[3];       /* added as T_end * background to the colour                           */
-  int32_t reserved;          /* must be 0                                                            */
-  void* d_work;              /* optional device scratch for the tile schedule (salf_render_work_size) */
-  size_t work_bytes;         /* its size; ignored when d_work is NULL                               */
+  int32_t schedule;          /* tile schedule: SALF_SCHEDULE_NONE, _BUILD or _REUSE (see below)      */
+  void* d_work;              /* schedule buffer (salf_render_work_size bytes, 256-byte aligned)      */
+  size_t work_bytes;         /* its size; both ignored with SALF_SCHEDULE_NONE                      */
 } salf_render_opts;
 
-/* Device bytes of the optional tile-schedule buffer (salf_render_opts.d_work) of a render of
- * `sensor` or of explicit `rays` (exactly one non-NULL).  With the buffer, salf_render and
- * salf_render_backward first estimate the cost of every 64-ray tile by walking its centre ray
- * through the root grid (for each occupied root cell, the length of the ray inside the bounds of
- * the cell's voxels divided by the size of its finest voxels, about the voxels it crosses), then
- * process the tiles heaviest first, which shortens the tail of the launch.  Outputs are the same
- * bits in any order.  Calls that may overlap must not share a buffer.  Errors: INVALID_ARG. */
+/* Tile schedules.  A render runs one wave per 64-ray tile.  A schedule estimates every tile's
+ * cost by walking its centre ray through the root grid (for each occupied root cell, the length
+ * of the ray inside the bounds of the cell's voxels divided by the size of its finest voxels,
+ * about the voxels it crosses) and orders the tiles heaviest first, which shortens the tail of
+ * the launch; a launch whose tiles all fit on the GPU at once keeps its own order.  Outputs are
+ * the same bits in any order.
+ *   SALF_SCHEDULE_NONE  tiles in index order; d_work is not used
+ *   SALF_SCHEDULE_BUILD salf_render / salf_render_backward build the schedule in d_work first
+ *   SALF_SCHEDULE_REUSE use the schedule already in d_work (built by salf_render_schedule or an
+ *                       earlier BUILD call); a schedule made for another ray layout (sensor size,
+ *                       tiling) is ignored.  The scene and pose may differ: only speed depends on it.
+ * Calls that may overlap must not share a buffer. */
+enum { SALF_SCHEDULE_NONE = 0, SALF_SCHEDULE_BUILD = 1, SALF_SCHEDULE_REUSE = 2 };
+
+/* Device bytes of the schedule buffer of a render of `sensor` or of explicit `rays` (exactly one
+ * non-NULL).  Errors: INVALID_ARG. */
 salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* rays, size_t* bytes);
+
+/* Build the tile schedule of a render of `sensor` or `rays` on scene `scene_id` into opts->d_work
+ * (opts->schedule is not used), asynchronously on `stream`.  Errors: INVALID_ARG, NOT_FOUND, DEVICE. */
+salf_status salf_render_schedule(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                                 const salf_rays* rays, const salf_render_opts* opts, void* stream);
 
 /* Per-ray outputs, device FP32 unless noted; a NULL pointer means "not wanted".
  *   rgb [n, 3]    C = sum w rgb + T_end * background   (Eq. 3)

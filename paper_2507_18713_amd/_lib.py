@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -
                 -6: "BUSY", -7: "UNSUPPORTED"}
 FIELD_CORNER, FIELD_PAPER = 0, 1
 SCENE_PREACTIVATE = 1
+SCHEDULE_NONE, SCHEDULE_BUILD, SCHEDULE_REUSE = 0, 1, 2
 PINHOLE, FISHEYE_EQUIDISTANT, LIDAR_SPINNING = 0, 1, 2
 
 
@@ -44,7 +45,7 @@ class Rays(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("samples_per_voxel", C.c_int32), ("t_min", C.c_float), ("background", C.c_float * 3),
-                ("reserved", C.c_int32), ("d_work", C.c_void_p), ("work_bytes", C.c_size_t)]
+                ("schedule", C.c_int32), ("d_work", C.c_void_p), ("work_bytes", C.c_size_t)]
 
 
 class Outputs(C.Structure):
@@ -88,6 +89,8 @@ SIGNATURES = {
     "salf_render": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(RenderOpts),
                                 C.POINTER(Outputs), C.c_void_p]),
     "salf_render_work_size": (C.c_int32, [C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(C.c_size_t)]),
+    "salf_render_schedule": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
+                                         C.POINTER(RenderOpts), C.c_void_p]),
     "salf_trace_hits": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Rays), C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "salf_render_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),

@@ -177,24 +177,54 @@ def generate_rays(sensor: dict, device="cuda") -> Dict[str, torch.Tensor]:
     return {"o": o, "d": d, "t": t, "valid": v}
 
 
-def _opts(samples, t_min, background, work: Optional[torch.Tensor] = None) -> _lib.RenderOpts:
+def _opts(samples, t_min, background, work: Optional[torch.Tensor] = None,
+          mode: int = _lib.SCHEDULE_NONE) -> _lib.RenderOpts:
     op = _lib.RenderOpts()
     op.samples_per_voxel = int(samples)
     op.t_min = float(t_min)
     op.background[:] = [float(x) for x in background]
-    op.reserved = 0
+    op.schedule = int(mode) if work is not None else _lib.SCHEDULE_NONE
     op.d_work = work.data_ptr() if work is not None else None
     op.work_bytes = work.numel() if work is not None else 0
     return op
 
 
 def _schedule_work(sen, rays, dev) -> torch.Tensor:
-    """Scratch for the heaviest-tiles-first schedule of one launch (from torch's stream-ordered
+    """An uninitialized schedule buffer for one launch layout (from torch's stream-ordered
     allocator, so launches on other streams never share it)."""
     n = C.c_size_t()
     call("salf_render_work_size", C.byref(sen) if sen is not None else None,
          C.byref(rays) if rays is not None else None, C.byref(n))
     return torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+
+
+def _schedule_args(schedule, sen, rays, dev):
+    """(buffer, mode) for the schedule argument of render / render_backward: True builds a
+    schedule in a fresh buffer during the call, a tensor from render_schedule is reused, False
+    renders tiles in index order."""
+    if isinstance(schedule, torch.Tensor):
+        return schedule, _lib.SCHEDULE_REUSE
+    if schedule:
+        return _schedule_work(sen, rays, dev), _lib.SCHEDULE_BUILD
+    return None, _lib.SCHEDULE_NONE
+
+
+def render_schedule(scene: "Scene", sensor: Optional[dict] = None, o: Optional[torch.Tensor] = None,
+                    d: Optional[torch.Tensor] = None, t_near: float = 0.0, t_far: float = math.inf,
+                    image_width: int = 0) -> torch.Tensor:
+    """Build the heaviest-tiles-first schedule of a render of `sensor` (or explicit rays) on
+    `scene` and return its buffer; pass it as `schedule=` to render / render_backward to reuse it
+    for renders with the same ray layout."""
+    dev = scene.device
+    sen = rays = None
+    if sensor is not None:
+        sen = sensor_struct(sensor)
+    else:
+        rays = _rays_struct(o, d, t_near, t_far, dev, image_width)
+    work = _schedule_work(sen, rays, dev)
+    call("salf_render_schedule", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
+         C.byref(rays) if rays is not None else None, C.byref(_opts(4, 1e-6, (0.0, 0.0, 0.0), work)), _stream(dev))
+    return work
 
 
 def _rays_struct(o, d, t_near, t_far, device, image_width=0):
@@ -217,10 +247,11 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
            d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
            outputs: Iterable[str] = ("rgb", "depth", "opacity"), t_near: float = 0.0, t_far: float = math.inf,
            out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0,
-           schedule: bool = True) -> Dict[str, torch.Tensor]:
+           schedule=True) -> Dict[str, torch.Tensor]:
     """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
     image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
-    schedule: process the launch's tiles heaviest first (same outputs, shorter tail).
+    schedule: True builds a heaviest-tiles-first schedule in the call, a buffer from
+    render_schedule reuses one, False keeps tile order (the outputs are the same bits).
     Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
     n_hits int32 [n])."""
     dev = scene.device
@@ -243,9 +274,9 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     ob = _lib.Outputs()
     for k in OUTPUT_NAMES:
         setattr(ob, k, res[k].data_ptr() if k in res else None)
-    work = _schedule_work(sen, rays, dev) if schedule else None
+    work, mode = _schedule_args(schedule, sen, rays, dev)
     call("salf_render", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work)),
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work, mode)),
          C.byref(ob), _stream(dev))
     return res
 
@@ -269,7 +300,7 @@ def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_
 def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[str, Optional[torch.Tensor]],
                     sensor: Optional[dict] = None, o=None, d=None, samples: int = 4, t_min: float = 1e-6,
                     background=(0.0, 0.0, 0.0), t_near: float = 0.0, t_far: float = math.inf,
-                    d_geo=None, d_rgb=None, d_int=None, image_width: int = 0, schedule: bool = True):
+                    d_geo=None, d_rgb=None, d_int=None, image_width: int = 0, schedule=True):
     """Accumulate dL/d(params) of a corner-field render into d_geo/d_rgb/d_int (allocated zeroed if
     None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
     dev = scene.device
@@ -295,9 +326,10 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
             t = t.contiguous()
             grads[k] = t
         setattr(g, f, t.data_ptr() if t is not None else None)
-    work = _schedule_work(sen, rays, dev) if schedule else None
+    work, mode = _schedule_args(schedule, sen, rays, dev)
     call("salf_render_backward", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work)), C.byref(sv),
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work, mode)),
+         C.byref(sv),
          C.byref(g), _ptr(d_geo), _ptr(d_rgb), _ptr(d_int), _stream(dev))
     return d_geo, d_rgb, d_int
 

@@ -110,7 +110,8 @@ salf_status salf::validate_opts(const salf_render_opts* o) {
     return set_error(SALF_ERR_INVALID_ARG, "samples_per_voxel %d outside [1, %d]", o->samples_per_voxel,
                      SALF_MAX_SAMPLES);
   if (!(o->t_min >= 0.0f) || !(o->t_min <= 1.0f)) return set_error(SALF_ERR_INVALID_ARG, "t_min must be in [0, 1]");
-  if (o->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->schedule < SALF_SCHEDULE_NONE || o->schedule > SALF_SCHEDULE_REUSE)
+    return set_error(SALF_ERR_INVALID_ARG, "schedule must be SALF_SCHEDULE_NONE, _BUILD or _REUSE");
   return SALF_OK;
 }
 
@@ -165,6 +166,17 @@ salf_status ray_layout(const salf_sensor* sensor, const salf_rays* rays, RenderP
   return SALF_OK;
 }
 
+// The schedule buffer of opts must hold the schedule of p's tiles.
+salf_status check_work(const salf_render_opts* opts, const RenderParams& p) {
+  const size_t need = tile_work_bytes(tile_count(p));
+  if (!opts->d_work) return set_error(SALF_ERR_INVALID_ARG, "a tile schedule needs a work buffer");
+  if (opts->work_bytes < need)
+    return set_error(SALF_ERR_INVALID_ARG, "work buffer holds %zu bytes; the tile schedule needs %zu",
+                     opts->work_bytes, need);
+  if ((uintptr_t)opts->d_work & 255u) return set_error(SALF_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
+  return SALF_OK;
+}
+
 // Fill the parts of RenderParams shared by render and backward.
 salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
                            const salf_render_opts* opts, RenderParams* p, int* field) {
@@ -175,12 +187,9 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
   memset(p, 0, sizeof(*p));
   if ((st = ray_layout(sensor, rays, p))) return st;
   p->scene = sc->view;
-  if (opts->d_work) {
-    const size_t need = tile_work_bytes(tile_count(*p));
-    if (opts->work_bytes < need)
-      return set_error(SALF_ERR_INVALID_ARG, "work buffer holds %zu bytes; the tile schedule needs %zu",
-                       opts->work_bytes, need);
-    if ((uintptr_t)opts->d_work & 255u) return set_error(SALF_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
+  if (opts->schedule != SALF_SCHEDULE_NONE) {
+    if ((st = check_work(opts, *p))) return st;
+    p->sched = (const int32_t*)opts->d_work;
   }
   p->S = opts->samples_per_voxel;
   p->t_min = opts->t_min;
@@ -377,8 +386,23 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
     return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
   p.out = *out;
   DeviceGuard g(ctx->device);
-  if ((st = check_hip(launch_tile_order(p, opts->d_work, (hipStream_t)stream), "tile schedule launch"))) return st;
+  if (opts->schedule == SALF_SCHEDULE_BUILD &&
+      (st = check_hip(launch_tile_schedule(p, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
+    return st;
   return check_hip(launch_render(p, field, (hipStream_t)stream), "render launch");
+}
+
+salf_status salf_render_schedule(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                                 const salf_rays* rays, const salf_render_opts* opts, void* stream) {
+  if (!opts) return set_error(SALF_ERR_INVALID_ARG, "render opts is NULL");
+  salf_render_opts o = *opts;
+  o.schedule = SALF_SCHEDULE_BUILD;
+  RenderParams p;
+  int field = 0;
+  salf_status st = prepare_render(ctx, scene_id, sensor, rays, &o, &p, &field);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  return check_hip(launch_tile_schedule(p, o.d_work, (hipStream_t)stream), "tile schedule launch");
 }
 
 salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* rays, size_t* bytes) {
@@ -429,7 +453,9 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
   b.drgb = d_drgb;
   b.dint = d_dint;
   DeviceGuard g(ctx->device);
-  if ((st = check_hip(launch_tile_order(b.fwd, opts->d_work, (hipStream_t)stream), "tile schedule launch"))) return st;
+  if (opts->schedule == SALF_SCHEDULE_BUILD &&
+      (st = check_hip(launch_tile_schedule(b.fwd, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
+    return st;
   return check_hip(launch_backward(b, (hipStream_t)stream), "backward launch");
 }
 

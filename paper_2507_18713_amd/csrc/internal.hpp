@@ -63,18 +63,21 @@ struct RenderParams {
   int32_t img_w, img_h;
   int32_t tiles_x, tiles_y;
   int32_t tw_log2;           // tile width 2^tw_log2, height 64 >> tw_log2
-  const int32_t* order;      // optional tile schedule: wave w renders tile order[w] (null: tile w)
+  const int32_t* sched;      // optional tile schedule (header + order, see launch_tile_schedule)
 };
+
+// int32 entries of the schedule buffer's header
+constexpr int kSchedHeader = 64;
 
 // Tiles (waves) of a launch: tiles_x * tiles_y when tiled, else groups of 64 consecutive rays.
 __host__ __device__ inline int64_t tile_count(const RenderParams& p) {
   return p.tiled ? (int64_t)p.tiles_x * p.tiles_y : (p.n + 63) / 64;
 }
 
-// Bytes of the tile-schedule buffer for n_tiles tiles, and the schedule itself: cost estimates,
-// a heaviest-first order written to the buffer and stored in p.order.
+// Bytes of the tile-schedule buffer for n_tiles tiles, and the schedule itself: cost estimates
+// and a heaviest-first order of p's tiles written to `work`, tagged with p's ray layout.
 size_t tile_work_bytes(int64_t n_tiles);
-hipError_t launch_tile_order(RenderParams& p, void* work, hipStream_t stream);
+hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream);
 
 // Tile shape of a wave: 8 x 8 pixels for cameras (and explicit rays with an image layout), 32
 // columns x 2 beams for a spinning LiDAR, whose neighbouring beams differ far more in path length

@@ -150,9 +150,15 @@ __device__ __forceinline__ bool lane_ray(const RenderParams& p, int64_t wave, in
   return true;
 }
 
-// Tile rendered by wave w of a launch: the schedule's entry when there is one.
+// Tile rendered by wave w of a launch: the schedule's entry when p carries a schedule built for
+// this launch's ray layout (its header must match), else w.
 __device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t w) {
-  return (p.order != nullptr && w < tile_count(p)) ? (int64_t)p.order[w] : w;
+  const int64_t nt = tile_count(p);
+  if (p.sched == nullptr || w >= nt) return w;
+  const int32_t* h = p.sched;
+  if (h[0] != (int32_t)nt || h[1] != (p.tiled | (p.tw_log2 << 8)) || h[2] != p.img_w) return w;
+  const int32_t t = h[kSchedHeader + h[3] + w];
+  return (t >= 0 && t < nt) ? (int64_t)t : w;
 }
 
 // Render the rays of one wave (tile `wave` of p) and store their outputs.  stk: this lane's node
@@ -196,49 +202,59 @@ __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
 }
 
 // ----------------------------------------------------------------------------- tile schedule
-// Heaviest tiles first (longest-processing-time-first list scheduling): a tile's cost is the sum
-// of the root-grid estimates of four probe rays (at the quarter points of the tile), quantized to
-// kCostBuckets logarithmic buckets; a counting sort over the buckets writes the order.  Ties are
-// placed in arbitrary order, which changes the schedule only, never a ray's result.  A launch
-// whose tiles all fit on the GPU at once keeps its own order (sorting would only crowd the heavy
-// tiles onto the same compute units).
+// Heaviest tiles first (longest-processing-time-first list scheduling).  A tile's cost is the
+// root-grid estimate of its centre ray, quantized to kCostBuckets logarithmic buckets; a counting
+// sort over the buckets writes the order (block-local histograms in LDS, one global atomic per
+// block and bucket).  Ties are placed in arbitrary order, which changes the schedule only, never
+// a ray's result.  A launch whose tiles all fit on the GPU at once keeps its own order (sorting
+// would only crowd the heavy tiles onto the same compute units): its schedule holds no order.
 constexpr int kCostBuckets = 256;
 
-__global__ void clear_u32(uint32_t* x, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0u;
+// Header of the schedule buffer: [0] tiles (0 = no order), [1] tiled | tw_log2 << 8, [2] img_w,
+// [3] offset of the order (int32 entries after the header); then keys, order, histogram, cursors.
+__global__ void sched_init(int32_t* h, int32_t n_tiles, int32_t layout, int32_t img_w, int32_t order_off,
+                           uint32_t* hist) {
+  for (int i = threadIdx.x; i < 2 * kCostBuckets; i += blockDim.x) hist[i] = 0u;
+  if (threadIdx.x == 0) {
+    h[0] = n_tiles;
+    h[1] = layout;
+    h[2] = img_w;
+    h[3] = order_off;
+  }
 }
 
-// Four lanes per tile, one probe each; the tile's cost is their sum.
 __global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, int64_t n_tiles, uint32_t* key,
                                                              uint32_t* hist) {
-  const int64_t tile = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 2;
-  const int probe = threadIdx.x & 3;
-  const int tw = p.tiled ? 1 << p.tw_log2 : 64, th = p.tiled ? 64 >> p.tw_log2 : 1;
-  const int lane = ((probe >> 1) ? (3 * th) / 4 : th / 4) * tw + ((probe & 1) ? (3 * tw) / 4 : tw / 4);
-  float cost = 0.0f;
+  static_assert(kThreads == kCostBuckets, "one thread per bucket");
+  __shared__ uint32_t local[kCostBuckets];
+  local[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t tile = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (tile < n_tiles) {
+    const int tw = p.tiled ? 1 << p.tw_log2 : 64, th = p.tiled ? 64 >> p.tw_log2 : 1;
     int64_t ray;
     float d[3];
     RayFrame f;
-    if (lane_ray(p, tile, lane, ray, d, f) || lane_ray(p, tile, 0, ray, d, f)) cost = root_cost(p.scene, f);
+    float cost = 0.0f;
+    if (lane_ray(p, tile, (th / 2) * tw + tw / 2, ray, d, f) || lane_ray(p, tile, 0, ray, d, f))
+      cost = root_cost(p.scene, f);
+    const int b = (int)(__log2f(1.0f + cost) * 16.0f);
+    const uint32_t bucket = (uint32_t)(b < 0 ? 0 : (b >= kCostBuckets ? kCostBuckets - 1 : b));
+    key[tile] = bucket;
+    atomicAdd(&local[bucket], 1u);
   }
-  cost += __shfl_xor(cost, 1);
-  cost += __shfl_xor(cost, 2);
-  if (tile >= n_tiles || probe != 0) return;
-  const int b = (int)(__log2f(1.0f + cost) * 16.0f);
-  const uint32_t bucket = (uint32_t)(b < 0 ? 0 : (b >= kCostBuckets ? kCostBuckets - 1 : b));
-  key[tile] = bucket;
-  atomicAdd(&hist[bucket], 1u);
+  __syncthreads();
+  if (local[threadIdx.x]) atomicAdd(&hist[threadIdx.x], local[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint32_t* key, int64_t n_tiles,
                                                               const uint32_t* hist, uint32_t* cursor, int32_t* order) {
-  static_assert(kThreads == kCostBuckets, "one thread per bucket");
-  __shared__ uint32_t above[kCostBuckets];
+  __shared__ uint32_t above[kCostBuckets], local[kCostBuckets], base[kCostBuckets];
   // above[b] = tiles in buckets heavier than b: an exclusive scan from the heaviest bucket down
   const int t = threadIdx.x;
   const uint32_t own = hist[kCostBuckets - 1 - t];
   above[t] = own;
+  local[t] = 0u;
   __syncthreads();
   for (int off = 1; off < kCostBuckets; off <<= 1) {
     const uint32_t add = t >= off ? above[t - off] : 0u;
@@ -249,11 +265,17 @@ __global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint32_t* ke
   const uint32_t excl = above[t] - own;
   __syncthreads();
   above[kCostBuckets - 1 - t] = excl;
-  __syncthreads();
+  // this block's tiles: rank within their bucket in the block, then one range per bucket
   const int64_t tile = blockIdx.x * (int64_t)kThreads + t;
-  if (tile >= n_tiles) return;
-  const uint32_t b = key[tile];
-  order[above[b] + atomicAdd(&cursor[b], 1u)] = (int32_t)tile;
+  uint32_t b = 0u, rank = 0u;
+  if (tile < n_tiles) {
+    b = key[tile];
+    rank = atomicAdd(&local[b], 1u);
+  }
+  __syncthreads();
+  if (local[t]) base[t] = atomicAdd(&cursor[t], local[t]);
+  __syncthreads();
+  if (tile < n_tiles) order[above[b] + base[b] + rank] = (int32_t)tile;
 }
 
 // Batched render of several requests in one launch: a grid sized to the GPU's resident capacity
@@ -529,13 +551,17 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 size_t tile_work_bytes(int64_t n_tiles) {
-  return 2 * align256((size_t)n_tiles * 4) + 2 * kCostBuckets * sizeof(uint32_t);
+  return kSchedHeader * 4 + 2 * align256((size_t)n_tiles * 4) + 2 * kCostBuckets * sizeof(uint32_t);
 }
 
-hipError_t launch_tile_order(RenderParams& p, void* work, hipStream_t stream) {
-  p.order = nullptr;
+hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream) {
   const int64_t n_tiles = tile_count(p);
-  if (work == nullptr || n_tiles <= 1) return hipSuccess;
+  char* w = (char*)work;
+  int32_t* hdr = (int32_t*)w;
+  uint32_t* key = (uint32_t*)(w + kSchedHeader * 4);
+  int32_t* order = (int32_t*)(w + kSchedHeader * 4 + align256((size_t)n_tiles * 4));
+  uint32_t* hist = (uint32_t*)(w + kSchedHeader * 4 + 2 * align256((size_t)n_tiles * 4));
+  uint32_t* cursor = hist + kCostBuckets;
   // waves the GPU holds at once: 4 SIMDs per compute unit, 4 waves each at the render kernels'
   // register use
   static int resident[64] = {0};
@@ -547,19 +573,16 @@ hipError_t launch_tile_order(RenderParams& p, void* work, hipStream_t stream) {
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     resident[dev] = 16 * (cus > 0 ? cus : 1);
   }
-  if (dev >= 0 && dev < 64 && n_tiles <= resident[dev]) return hipSuccess;
-  char* w = (char*)work;
-  uint32_t* key = (uint32_t*)w;
-  int32_t* order = (int32_t*)(w + align256((size_t)n_tiles * 4));
-  uint32_t* hist = (uint32_t*)(w + 2 * align256((size_t)n_tiles * 4));
-  uint32_t* cursor = hist + kCostBuckets;
-  const unsigned blocks = (unsigned)((n_tiles + kThreads - 1) / kThreads);
-  clear_u32<<<1, 256, 0, stream>>>(hist, 2 * kCostBuckets);
-  tile_cost_kernel<<<(unsigned)((4 * n_tiles + kThreads - 1) / kThreads), kThreads, 0, stream>>>(p, n_tiles, key, hist);
-  tile_order_kernel<<<blocks, kThreads, 0, stream>>>(key, n_tiles, hist, cursor, order);
-  e = hipGetLastError();
-  if (e == hipSuccess) p.order = order;
-  return e;
+  const bool sort = n_tiles > 1 && !(dev >= 0 && dev < 64 && n_tiles <= resident[dev]);
+  const int32_t order_off = (int32_t)(align256((size_t)n_tiles * 4) / 4);
+  sched_init<<<1, 256, 0, stream>>>(hdr, sort ? (int32_t)n_tiles : 0, p.tiled | (p.tw_log2 << 8), p.img_w, order_off,
+                                    hist);
+  if (sort) {
+    const unsigned blocks = (unsigned)((n_tiles + kThreads - 1) / kThreads);
+    tile_cost_kernel<<<blocks, kThreads, 0, stream>>>(p, n_tiles, key, hist);
+    tile_order_kernel<<<blocks, kThreads, 0, stream>>>(key, n_tiles, hist, cursor, order);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {

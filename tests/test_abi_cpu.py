@@ -47,7 +47,7 @@ int main(void) {
   printf("SceneStats %zu %zu\n", sizeof(salf_scene_stats), offsetof(salf_scene_stats, workspace_bytes));
   printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
   printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
-  printf("RenderOpts %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, reserved), offsetof(salf_render_opts, work_bytes));
+  printf("RenderOpts %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, schedule), offsetof(salf_render_opts, work_bytes));
   printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
   printf("ServerOpts %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight));
@@ -68,7 +68,7 @@ int main(void) {
         "SceneStats": [C.sizeof(S.SceneStats), S.SceneStats.workspace_bytes.offset],
         "Sensor": [C.sizeof(S.Sensor), S.Sensor.R0.offset, S.Sensor.t_far.offset],
         "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
-        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.reserved.offset, S.RenderOpts.work_bytes.offset],
+        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.schedule.offset, S.RenderOpts.work_bytes.offset],
         "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
         "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset],
@@ -133,16 +133,17 @@ def test_render_work_size_host_logic(L):
     n = C.c_size_t()
     up = lambda x: (x + 255) // 256 * 256
     # camera: 8x8 tiles; LiDAR: 32 columns x 2 beams; explicit rays: groups of 64 (or 8x8 tiles of
-    # an image layout); per tile a cost key and an order entry, plus two 256-entry histograms
+    # an image layout); a 256-byte header, per tile a cost key and an order entry, plus two
+    # 256-entry histograms
     for s, tiles in ((synth.config1_camera(), 240 * 135), (synth.config2_lidar(), 64 * 32)):
         assert lib.salf_render_work_size(C.byref(sensor_struct(s)), None, C.byref(n)) == 0
-        assert n.value == 2 * up(tiles * 4) + 2048
+        assert n.value == 256 + 2 * up(tiles * 4) + 2048
     r = L.Rays()
     r.o, r.d = 256, 512  # never dereferenced by a size query
     r.n, r.t_near, r.t_far, r.image_width = 1000, 0.0, math.inf, 0
-    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 2 * up(16 * 4) + 2048
+    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 256 + 2 * up(16 * 4) + 2048
     r.image_width = 50  # 50 x 20 image: 7 x 3 tiles
-    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 2 * up(21 * 4) + 2048
+    assert lib.salf_render_work_size(None, C.byref(r), C.byref(n)) == 0 and n.value == 256 + 2 * up(21 * 4) + 2048
     assert lib.salf_render_work_size(None, None, C.byref(n)) == -1
     assert lib.salf_render_work_size(C.byref(sensor_struct(synth.config1_camera())), C.byref(r), C.byref(n)) == -1
 

@@ -127,3 +127,13 @@ def test_tile_schedule_changes_nothing_but_the_order(salf, c1):
     a = salf.render(scene, o=rays["o"], d=rays["d"], outputs=("rgb", "n_hits"), schedule=True)
     b = salf.render(scene, o=rays["o"], d=rays["d"], outputs=("rgb", "n_hits"), schedule=False)
     assert torch.equal(a["rgb"], b["rgb"]) and torch.equal(a["n_hits"], b["n_hits"])
+    # a schedule built once and reused; one built for another ray layout is ignored
+    cam = synth.config1_camera()
+    buf = salf.render_schedule(scene, sensor=cam)
+    ref = salf.render(scene, sensor=cam, outputs=("rgb", "n_hits"), schedule=False)
+    for _ in range(2):
+        r = salf.render(scene, sensor=cam, outputs=("rgb", "n_hits"), schedule=buf)
+        assert torch.equal(r["rgb"], ref["rgb"]) and torch.equal(r["n_hits"], ref["n_hits"])
+    small = synth.config1_camera(960, 540)
+    r = salf.render(scene, sensor=small, outputs=("rgb",), schedule=buf)
+    assert torch.equal(r["rgb"], salf.render(scene, sensor=small, outputs=("rgb",), schedule=False)["rgb"])
