@@ -392,7 +392,9 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
 // Estimated number of voxels a ray crosses, from the root grid alone (used to schedule tiles):
 // for every occupied root cell on the ray, the length inside the bounds of the cell's voxels
 // times 2^(finest level in the cell) / root-cell size, plus a quarter per root cell visited.
-__device__ inline float root_cost(const SceneView& s, const RayFrame& f) {
+// Only the part of the ray's path through the grid between fractions lo and hi of its length is
+// walked, so that several lanes can share one ray.
+__device__ inline float root_cost(const SceneView& s, const RayFrame& f, float lo, float hi) {
   if (!f.valid) return 0.0f;
   const int K = s.K;
   float t, t_exit;
@@ -400,6 +402,11 @@ __device__ inline float root_cost(const SceneView& s, const RayFrame& f) {
     const int32_t glo[3] = {0, 0, 0};
     const int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
     if (!box_interval(f, glo, ghi, t, t_exit) || !(t < t_exit)) return 0.0f;
+    const float span = t_exit - t;
+    const float t1 = hi >= 1.0f ? t_exit : t + span * hi;
+    t = t + span * lo;
+    t_exit = t1;
+    if (!(t < t_exit)) return 0.0f;
   }
   RootAxis ax, ay, az;
   root_axis_init<0>(f, s, t, ax);

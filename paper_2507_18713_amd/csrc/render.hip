@@ -223,21 +223,29 @@ __global__ void sched_init(int32_t* h, int32_t n_tiles, int32_t layout, int32_t 
   }
 }
 
+// kCostLanes lanes per tile walk consecutive pieces of its centre ray; the tile's cost is their sum.
+constexpr int kCostLanes = 8;
+
 __global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, int64_t n_tiles, uint32_t* key,
                                                              uint32_t* hist) {
   static_assert(kThreads == kCostBuckets, "one thread per bucket");
   __shared__ uint32_t local[kCostBuckets];
   local[threadIdx.x] = 0u;
   __syncthreads();
-  const int64_t tile = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t tile = (blockIdx.x * (int64_t)kThreads + threadIdx.x) / kCostLanes;
+  const int piece = threadIdx.x % kCostLanes;
+  float cost = 0.0f;
   if (tile < n_tiles) {
     const int tw = p.tiled ? 1 << p.tw_log2 : 64, th = p.tiled ? 64 >> p.tw_log2 : 1;
     int64_t ray;
     float d[3];
     RayFrame f;
-    float cost = 0.0f;
     if (lane_ray(p, tile, (th / 2) * tw + tw / 2, ray, d, f) || lane_ray(p, tile, 0, ray, d, f))
-      cost = root_cost(p.scene, f);
+      cost = root_cost(p.scene, f, (float)piece / kCostLanes, (float)(piece + 1) / kCostLanes);
+  }
+#pragma unroll
+  for (int m = 1; m < kCostLanes; m <<= 1) cost += __shfl_xor(cost, m);
+  if (tile < n_tiles && piece == 0) {
     const int b = (int)(__log2f(1.0f + cost) * 16.0f);
     const uint32_t bucket = (uint32_t)(b < 0 ? 0 : (b >= kCostBuckets ? kCostBuckets - 1 : b));
     key[tile] = bucket;
@@ -579,7 +587,8 @@ hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t s
                                     hist);
   if (sort) {
     const unsigned blocks = (unsigned)((n_tiles + kThreads - 1) / kThreads);
-    tile_cost_kernel<<<blocks, kThreads, 0, stream>>>(p, n_tiles, key, hist);
+    tile_cost_kernel<<<(unsigned)((n_tiles * kCostLanes + kThreads - 1) / kThreads), kThreads, 0, stream>>>(
+        p, n_tiles, key, hist);
     tile_order_kernel<<<blocks, kThreads, 0, stream>>>(key, n_tiles, hist, cursor, order);
   }
   return hipGetLastError();
