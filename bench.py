@@ -233,12 +233,13 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     """1,048,576 rays per batch on the driving scene: 80% camera pixels drawn from 8 random views,
     20% LiDAR rays from 2 sweeps; loss = mean squared colour error + mean absolute depth error
     against targets rendered from a perturbed copy (logits + N(0, 0.1^2)).  A step = zero the
-    gradients, forward, loss gradients, hand-written backward."""
+    gradients, forward, loss gradients, hand-written backward, an SGD update of every corner logit
+    and the refresh of the activated corner values the renders read."""
     import numpy as np
 
     import synth
     rng = np.random.default_rng(seed)
-    scene = salf.Scene.from_data(data, device=dev)
+    scene = salf.Scene.from_data(data, device=dev, preactivate=True)
     pert = synth.SceneData(**{**data.__dict__})
     prng = np.random.default_rng(5)
     pert.z_geo = (data.z_geo + prng.normal(0, 0.1, data.z_geo.shape)).astype(np.float32)
@@ -280,6 +281,7 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     tgt_d = salf.render(target_scene, o=ol, d=dl, outputs=("depth",), **opts)["depth"]
     d_geo, d_rgb, d_int = (torch.zeros_like(t) for t in (scene.geo, scene.rgb, scene.intensity))
     saved_outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
+    lr = 100.0
 
     def step(ev=None):
         d_geo.zero_()
@@ -292,6 +294,9 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
             ev.record()
         salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
         salf.render_backward(scene, fl, {"depth": g_l}, o=ol, d=dl, d_geo=d_geo, **opts)
+        scene.geo.sub_(lr * d_geo)
+        scene.rgb.sub_(lr * d_rgb)
+        scene.refresh()
         return fc, fl
 
     for _ in range(2):
@@ -309,7 +314,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
     ms = float(np.median(times))
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
-                        "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy",
+                        "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
+                        "SGD update + activation refresh in the step",
             "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),

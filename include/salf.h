@@ -306,8 +306,11 @@ typedef struct {
  * `sensor`/`rays`, `opts` and the scene parameters must be those of the forward call, and
  * `saved` must hold its t_end and n_hits (rgb/depth/intensity as well when their gradient is
  * requested).  The kernel re-traverses each ray and recomputes transmittance front to back; no
- * per-sample state is stored.  Accumulation uses FP32 atomics, so the summation order (and the
- * last bits) vary between runs.  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field),
+ * per-sample state is stored.  A SALF_SCENE_PREACTIVATE scene is read through its stored
+ * activated values in both passes (salf_scene_refresh after changing the logits), softplus'
+ * being taken as 1 - exp(-softplus); the gradient is w.r.t. the logits either way.  Lanes of a
+ * wave that hit the same voxel add their contributions first; the rest is accumulated with FP32
+ * atomics, so the summation order (and the last bits) vary between runs.  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field),
  * DEVICE. */
 salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
                                  const salf_rays* rays, const salf_render_opts* opts,

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void raygen_kernel(salf_sensor s, float* 
 // dsigma_j = dL/dtau_j * delta_j, dc_j = gC w_j, di_j = gI w_j; corner logits get these times
 // the trilinear weight and the activation's derivative (softplus' = sigmoid, sigmoid' = s(1-s)).
 // Transmittance is recomputed front to back; the ray stops after the saved number of voxels.
-template <bool RGB, bool INT>
+template <bool RGB, bool INT, bool ACT>
 __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const RenderParams& p = b.fwd;
   int64_t ray;
@@ -414,31 +414,35 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
-    float zg[8], sp[8], zr[3][8], cr[3][8], zi[8], ci[8];
+    // activated corner values (stored ones when the scene keeps them, else from the logits) and
+    // softplus' = sigmoid for density: with stored values sigmoid(z) = 1 - exp(-softplus(z))
+    float sp[8], dsp[8], cr[3][8], ci[8];
     {
-      const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
+      const float4* gp = reinterpret_cast<const float4*>((ACT ? s.act_geo : s.geo) + (int64_t)v * 8);
       const float4 g0 = gp[0], g1 = gp[1];
-      zg[0] = g0.x; zg[1] = g0.y; zg[2] = g0.z; zg[3] = g0.w; zg[4] = g1.x; zg[5] = g1.y; zg[6] = g1.z; zg[7] = g1.w;
-    }
+      const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sp[i] = softplus_f(zg[i]);
+      for (int i = 0; i < 8; ++i) {
+        sp[i] = ACT ? g[i] : softplus_f(g[i]);
+        dsp[i] = ACT ? -expm1f(-g[i]) : sigmoid_f(g[i]);
+      }
+    }
     if (RGB) {
-      const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
+      const float4* cp = reinterpret_cast<const float4*>((ACT ? s.act_rgb : s.rgb) + (int64_t)v * 24);
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         const float4 a = cp[2 * ch], q = cp[2 * ch + 1];
-        zr[ch][0] = a.x; zr[ch][1] = a.y; zr[ch][2] = a.z; zr[ch][3] = a.w;
-        zr[ch][4] = q.x; zr[ch][5] = q.y; zr[ch][6] = q.z; zr[ch][7] = q.w;
+        const float z[8] = {a.x, a.y, a.z, a.w, q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cr[ch][i] = sigmoid_f(zr[ch][i]);
+        for (int i = 0; i < 8; ++i) cr[ch][i] = ACT ? z[i] : sigmoid_f(z[i]);
       }
     }
     if (INT) {
-      const float4* ip = reinterpret_cast<const float4*>(s.inten + (int64_t)v * 8);
+      const float4* ip = reinterpret_cast<const float4*>((ACT ? s.act_int : s.inten) + (int64_t)v * 8);
       const float4 a = ip[0], q = ip[1];
-      zi[0] = a.x; zi[1] = a.y; zi[2] = a.z; zi[3] = a.w; zi[4] = q.x; zi[5] = q.y; zi[6] = q.z; zi[7] = q.w;
+      const float z[8] = {a.x, a.y, a.z, a.w, q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) ci[i] = sigmoid_f(zi[i]);
+      for (int i = 0; i < 8; ++i) ci[i] = ACT ? z[i] : sigmoid_f(z[i]);
     }
     float rel[3], stp[3], delta, sc;
     segment_frame(s, f, h, rS, rel, stp, delta, sc);
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     // this lane's gradient row for the voxel (activation derivative applied): 8 density corners,
     // then 24 colour and 8 intensity corners when present
 #pragma unroll
-    for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * sigmoid_f(zg[i]);
+    for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * dsp[i];
     if (RGB) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch)
@@ -627,10 +631,17 @@ hipError_t launch_backward(const BackwardParams& b, hipStream_t stream) {
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
   const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
-  if (rgb && in) backward_kernel<true, true><<<blocks, kThreads, 0, stream>>>(b);
-  else if (rgb) backward_kernel<true, false><<<blocks, kThreads, 0, stream>>>(b);
-  else if (in) backward_kernel<false, true><<<blocks, kThreads, 0, stream>>>(b);
-  else backward_kernel<false, false><<<blocks, kThreads, 0, stream>>>(b);
+  if (p.scene.act_geo != nullptr) {
+    if (rgb && in) backward_kernel<true, true, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, true><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, true><<<blocks, kThreads, 0, stream>>>(b);
+  } else {
+    if (rgb && in) backward_kernel<true, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+  }
   return hipGetLastError();
 }
 

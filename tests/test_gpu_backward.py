@@ -194,3 +194,34 @@ def test_autograd_function(salf):
     assert torch.allclose(dg, scene.geo.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(dr, scene.rgb.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(di, scene.intensity.grad, rtol=1e-4, atol=1e-6)
+
+
+def test_preactivated_scene_gives_the_same_gradient(salf):
+    """A scene that keeps activated corner values renders and differentiates from them (softplus'
+    taken as 1 - exp(-softplus)); gradients w.r.t. the raw logits match the raw-logit scene's, also
+    after the logits change and the scene is refreshed."""
+    data = synth.random_scene(97, root_dims=(5, 4, 3), max_level=2)
+    raw = salf.Scene.from_data(data, device=dev())
+    act = salf.Scene.from_data(data, device=dev(), preactivate=True)
+    o, d = synth.random_rays(98, 512, data.origin, data.origin + data.root_dims * data.root_size)
+    o, d = to_dev(o), to_dev(d)
+    opts = dict(samples=4, t_min=1e-6)
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    for step in range(2):
+        if step == 1:  # change the logits of both scenes in place, refresh the stored activations
+            for sc in (raw, act):
+                sc.geo.mul_(1.1).add_(0.05)
+                sc.rgb.mul_(0.9)
+                sc.intensity.add_(0.1)
+            act.refresh()
+        sr = salf.render(raw, o=o, d=d, outputs=outs, **opts)
+        sa = salf.render(act, o=o, d=d, outputs=outs, **opts)
+        for k in ("rgb", "depth", "opacity", "intensity"):
+            assert torch.allclose(sr[k], sa[k], rtol=1e-5, atol=1e-6), k
+        grads = {"rgb": torch.cos(3 * sr["rgb"]), "depth": 0.1 * torch.sign(sr["depth"] - 1.0),
+                 "opacity": torch.ones_like(sr["opacity"]), "intensity": 0.5 * torch.ones_like(sr["intensity"])}
+        gr = salf.render_backward(raw, sr, dict(grads), o=o, d=d, **opts)
+        ga = salf.render_backward(act, sa, dict(grads), o=o, d=d, **opts)
+        for name, x, y in zip(("geo", "rgb", "intensity"), gr, ga):
+            assert torch.any(x != 0), name
+            _close(y.cpu().numpy(), x.cpu().numpy(), rel=1e-3, absr=1e-5)
