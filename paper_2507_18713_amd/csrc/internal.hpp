@@ -100,9 +100,17 @@ struct BatchItem {
   int32_t pad;
 };
 // d_items: device array of n_items requests sorted by tile_begin (the first begins at 0);
-// d_counter: a zeroed device word the waves pull tiles from.
+// d_counter: a zeroed device word the waves pull tiles from; d_sched: a batch schedule built by
+// launch_batch_schedule for these items (or null: tiles in request order).
 hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
-                               hipStream_t stream);
+                               const int32_t* d_sched, hipStream_t stream);
+// Heaviest-first schedule of the n_tiles global tiles of a batch, in a buffer of
+// tile_work_bytes(kBatchScheduleTiles) bytes.  Larger batches (more than about four 1920x1080
+// frames) keep request order: their tail is short next to their length, and interleaving the
+// tiles of many frames and scenes costs cache locality.
+constexpr int64_t kBatchScheduleTiles = (int64_t)1 << 17;
+hipError_t launch_batch_schedule(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, void* work,
+                                 hipStream_t stream);
 hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int32_t* counts, int32_t* ids,
                         float* t_in, float* t_out, hipStream_t stream);
 hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uint8_t* valid, hipStream_t stream);

@@ -5,6 +5,8 @@
 // Work mapping: one lane per ray.  In sensor mode a wave64 covers a tile of 64 neighbouring rays
 // (8x8 pixels; 32 columns x 2 beams of a LiDAR) so that the lanes of a wave walk nearby voxels and
 // share their parameter cache lines; ray generation is fused (no ray buffer in HBM).
+#include <string.h>
+
 #include "internal.hpp"
 
 namespace salf {
@@ -201,6 +203,17 @@ __global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
   render_wave<FIELD, RGB, INT>(p, scheduled_tile(p, w), stk + threadIdx.x);
 }
 
+// Request of global tile `tile` in a batch (items sorted by tile_begin, the first at 0).
+__device__ __forceinline__ int find_item(const BatchItem* items, int32_t n_items, int64_t tile) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ----------------------------------------------------------------------------- tile schedule
 // Heaviest tiles first (longest-processing-time-first list scheduling).  A tile's cost is the
 // root-grid estimate of its centre ray, quantized to kCostBuckets logarithmic buckets; a counting
@@ -226,8 +239,9 @@ __global__ void sched_init(int32_t* h, int32_t n_tiles, int32_t layout, int32_t 
 // kCostLanes lanes per tile walk consecutive pieces of its centre ray; the tile's cost is their sum.
 constexpr int kCostLanes = 8;
 
-__global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, int64_t n_tiles, uint32_t* key,
-                                                             uint32_t* hist) {
+// Tiles of one launch (items == nullptr) or the global tiles of a batch of requests.
+__global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, const BatchItem* items, int32_t n_items,
+                                                             int64_t n_tiles, uint32_t* key, uint32_t* hist) {
   static_assert(kThreads == kCostBuckets, "one thread per bucket");
   __shared__ uint32_t local[kCostBuckets];
   local[threadIdx.x] = 0u;
@@ -236,12 +250,19 @@ __global__ __launch_bounds__(kThreads) void tile_cost_kernel(RenderParams p, int
   const int piece = threadIdx.x % kCostLanes;
   float cost = 0.0f;
   if (tile < n_tiles) {
-    const int tw = p.tiled ? 1 << p.tw_log2 : 64, th = p.tiled ? 64 >> p.tw_log2 : 1;
+    const RenderParams* q = &p;
+    int64_t lt = tile;
+    if (items != nullptr) {
+      const int r = find_item(items, n_items, tile);
+      q = &items[r].p;
+      lt = tile - items[r].tile_begin;
+    }
+    const int tw = q->tiled ? 1 << q->tw_log2 : 64, th = q->tiled ? 64 >> q->tw_log2 : 1;
     int64_t ray;
     float d[3];
     RayFrame f;
-    if (lane_ray(p, tile, (th / 2) * tw + tw / 2, ray, d, f) || lane_ray(p, tile, 0, ray, d, f))
-      cost = root_cost(p.scene, f, (float)piece / kCostLanes, (float)(piece + 1) / kCostLanes);
+    if (lane_ray(*q, lt, (th / 2) * tw + tw / 2, ray, d, f) || lane_ray(*q, lt, 0, ray, d, f))
+      cost = root_cost(q->scene, f, (float)piece / kCostLanes, (float)(piece + 1) / kCostLanes);
   }
 #pragma unroll
   for (int m = 1; m < kCostLanes; m <<= 1) cost += __shfl_xor(cost, m);
@@ -291,21 +312,22 @@ __global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint32_t* ke
 // (each wave's exit condition is that counter passing the tile count).  The request of a tile is
 // found by binary search over the requests' first tiles; its shading variant is uniform per wave.
 __global__ __launch_bounds__(kThreads) void render_batch_kernel(const BatchItem* items, int32_t n_items,
-                                                                int64_t n_tiles, uint32_t* counter) {
+                                                                int64_t n_tiles, uint32_t* counter,
+                                                                const int32_t* sched) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   const int lane = threadIdx.x & 63;
+  const bool ordered = sched != nullptr && sched[0] == (int32_t)n_tiles;
   for (;;) {
     uint32_t t = 0;
     if (lane == 0) t = atomicAdd(counter, 1u);
-    const int64_t tile = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-    if (tile >= n_tiles) break;
-    int lo = 0, hi = n_items - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (items[mid].tile_begin <= tile) lo = mid;
-      else hi = mid - 1;
+    const int64_t slot = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    if (slot >= n_tiles) break;
+    int64_t tile = slot;
+    if (ordered) {
+      const int32_t o = sched[kSchedHeader + sched[3] + slot];
+      if (o >= 0 && o < n_tiles) tile = o;
     }
-    const BatchItem& b = items[lo];
+    const BatchItem& b = items[find_item(items, n_items, tile)];
     const int64_t w = tile - b.tile_begin;
     switch (b.variant) {
       case 0: render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x); break;
@@ -566,14 +588,10 @@ size_t tile_work_bytes(int64_t n_tiles) {
   return kSchedHeader * 4 + 2 * align256((size_t)n_tiles * 4) + 2 * kCostBuckets * sizeof(uint32_t);
 }
 
-hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream) {
-  const int64_t n_tiles = tile_count(p);
-  char* w = (char*)work;
-  int32_t* hdr = (int32_t*)w;
-  uint32_t* key = (uint32_t*)(w + kSchedHeader * 4);
-  int32_t* order = (int32_t*)(w + kSchedHeader * 4 + align256((size_t)n_tiles * 4));
-  uint32_t* hist = (uint32_t*)(w + kSchedHeader * 4 + 2 * align256((size_t)n_tiles * 4));
-  uint32_t* cursor = hist + kCostBuckets;
+namespace {
+// Schedule of the tiles of one launch (items == nullptr: p's tiles) or of a batch of requests.
+hipError_t schedule_tiles(const RenderParams& p, const BatchItem* items, int32_t n_items, int64_t n_tiles,
+                          int64_t capacity, void* work, hipStream_t stream) {
   // waves the GPU holds at once: 4 SIMDs per compute unit, 4 waves each at the render kernels'
   // register use
   static int resident[64] = {0};
@@ -585,17 +603,40 @@ hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t s
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     resident[dev] = 16 * (cus > 0 ? cus : 1);
   }
-  const bool sort = n_tiles > 1 && !(dev >= 0 && dev < 64 && n_tiles <= resident[dev]);
-  const int32_t order_off = (int32_t)(align256((size_t)n_tiles * 4) / 4);
+  // no order for a launch that fits on the GPU at once or exceeds the buffer's capacity; the
+  // buffer then holds only the header and the (unused) histograms
+  const bool sort = n_tiles > 1 && n_tiles <= capacity && !(dev >= 0 && dev < 64 && n_tiles <= resident[dev]);
+  const int64_t lay = sort ? n_tiles : 0;
+  char* w = (char*)work;
+  int32_t* hdr = (int32_t*)w;
+  uint32_t* key = (uint32_t*)(w + kSchedHeader * 4);
+  int32_t* order = (int32_t*)(w + kSchedHeader * 4 + align256((size_t)lay * 4));
+  uint32_t* hist = (uint32_t*)(w + kSchedHeader * 4 + 2 * align256((size_t)lay * 4));
+  uint32_t* cursor = hist + kCostBuckets;
+  const int32_t order_off = (int32_t)(align256((size_t)lay * 4) / 4);
   sched_init<<<1, 256, 0, stream>>>(hdr, sort ? (int32_t)n_tiles : 0, p.tiled | (p.tw_log2 << 8), p.img_w, order_off,
                                     hist);
   if (sort) {
     const unsigned blocks = (unsigned)((n_tiles + kThreads - 1) / kThreads);
     tile_cost_kernel<<<(unsigned)((n_tiles * kCostLanes + kThreads - 1) / kThreads), kThreads, 0, stream>>>(
-        p, n_tiles, key, hist);
+        p, items, n_items, n_tiles, key, hist);
     tile_order_kernel<<<blocks, kThreads, 0, stream>>>(key, n_tiles, hist, cursor, order);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream) {
+  const int64_t n_tiles = tile_count(p);
+  return schedule_tiles(p, nullptr, 0, n_tiles, n_tiles, work, stream);
+}
+
+hipError_t launch_batch_schedule(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, void* work,
+                                 hipStream_t stream) {
+  RenderParams none;
+  memset(&none, 0, sizeof(none));
+  return schedule_tiles(none, d_items, n_items, n_tiles, kBatchScheduleTiles, work, stream);
 }
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
@@ -608,7 +649,7 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
 }
 
 hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
-                               hipStream_t stream) {
+                               const int32_t* d_sched, hipStream_t stream) {
   if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
   static int resident_blocks = 0;  // blocks of this kernel the whole GPU keeps resident
   if (resident_blocks == 0) {
@@ -621,7 +662,7 @@ hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_
   }
   const int64_t want = (n_tiles + 3) / 4;  // 4 waves per block
   const unsigned blocks = (unsigned)(want < resident_blocks ? want : resident_blocks);
-  render_batch_kernel<<<blocks, kThreads, 0, stream>>>(d_items, n_items, n_tiles, d_counter);
+  render_batch_kernel<<<blocks, kThreads, 0, stream>>>(d_items, n_items, n_tiles, d_counter, d_sched);
   return hipGetLastError();
 }
 

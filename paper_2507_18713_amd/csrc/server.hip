@@ -124,9 +124,12 @@ struct Slot {
   uint32_t zero = 0;
   BatchItem* d_items = nullptr;
   uint32_t* d_counter = nullptr;
+  void* d_sched = nullptr;  // heaviest-first order of the launch's tiles
 };
 
-size_t slot_bytes(int max_batch) { return align_up((size_t)max_batch * sizeof(BatchItem)) + kAlign; }
+size_t slot_bytes(int max_batch) {
+  return align_up((size_t)max_batch * sizeof(BatchItem)) + kAlign + align_up(tile_work_bytes(kBatchScheduleTiles));
+}
 
 }  // namespace
 }  // namespace salf
@@ -175,7 +178,10 @@ bool salf_server::launch(Slot& s) {
   hipError_t e = hipMemcpyAsync(s.d_items, s.items.data(), s.items.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
                                 s.stream);
   if (e == hipSuccess) e = hipMemcpyAsync(s.d_counter, &s.zero, sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
-  if (e == hipSuccess) e = launch_render_batch(s.d_items, (int32_t)s.items.size(), tiles, s.d_counter, s.stream);
+  if (e == hipSuccess) e = launch_batch_schedule(s.d_items, (int32_t)s.items.size(), tiles, s.d_sched, s.stream);
+  if (e == hipSuccess)
+    e = launch_render_batch(s.d_items, (int32_t)s.items.size(), tiles, s.d_counter, (const int32_t*)s.d_sched,
+                            s.stream);
   if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
   if (e != hipSuccess) {
     const double t = now_s();
@@ -292,6 +298,7 @@ salf_status salf_server_create(salf_context* ctx, const salf_server_opts* opts, 
     char* w = (char*)opts->d_work + (size_t)i * slot_bytes(opts->max_batch);
     sl.d_items = (BatchItem*)w;
     sl.d_counter = (uint32_t*)(w + align_up((size_t)opts->max_batch * sizeof(BatchItem)));
+    sl.d_sched = w + align_up((size_t)opts->max_batch * sizeof(BatchItem)) + kAlign;
     hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.event, hipEventDisableTiming);
     if (e != hipSuccess) {
