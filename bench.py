@@ -365,7 +365,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path runs on a single "
-              f"GPU; sharding across GPUs is described in DESIGN.md but not built)", file=sys.stderr)
+              f"GPU; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
