@@ -108,7 +108,7 @@ const char* salf_last_error(void);
 salf_status salf_create(int32_t hip_device, salf_context** out);
 
 /* Destroy a context and forget its scenes (their workspaces stay owned by the caller).
- * Errors: INVALID_ARG. */
+ * Errors: INVALID_ARG, BUSY (a server created on it is still alive). */
 salf_status salf_destroy(salf_context* ctx);
 
 /* Synchronize `stream` and report any fault raised by kernels enqueued on it. Errors: DEVICE. */

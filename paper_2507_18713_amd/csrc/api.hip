@@ -220,6 +220,10 @@ salf_status salf_create(int32_t hip_device, salf_context** out) {
 
 salf_status salf_destroy(salf_context* ctx) {
   if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->servers > 0) return set_error(SALF_ERR_BUSY, "%d server(s) still use this context", ctx->servers);
+  }
   delete ctx;
   return SALF_OK;
 }

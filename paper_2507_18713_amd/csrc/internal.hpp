@@ -140,6 +140,7 @@ struct salf_context {
   int device = 0;
   std::mutex mu;
   std::vector<salf::Scene> scenes;
+  int servers = 0;  // live servers on this context (under mu); the context outlives them
 };
 
 namespace salf {

@@ -7,6 +7,8 @@
 // share their parameter cache lines; ray generation is fused (no ray buffer in HBM).
 #include <string.h>
 
+#include <atomic>
+
 #include "internal.hpp"
 
 namespace salf {
@@ -593,19 +595,21 @@ namespace {
 hipError_t schedule_tiles(const RenderParams& p, const BatchItem* items, int32_t n_items, int64_t n_tiles,
                           int64_t capacity, void* work, hipStream_t stream) {
   // waves the GPU holds at once: 4 SIMDs per compute unit, 4 waves each at the render kernels'
-  // register use
-  static int resident[64] = {0};
+  // register use (per device, queried once; concurrent first calls only repeat the query)
+  static std::atomic<int> resident[64];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev >= 0 && dev < 64 && resident[dev] == 0) {
+  int held = (dev >= 0 && dev < 64) ? resident[dev].load(std::memory_order_relaxed) : 0;
+  if (held == 0) {
     int cus = 0;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    resident[dev] = 16 * (cus > 0 ? cus : 1);
+    held = 16 * (cus > 0 ? cus : 1);
+    if (dev >= 0 && dev < 64) resident[dev].store(held, std::memory_order_relaxed);
   }
   // no order for a launch that fits on the GPU at once or exceeds the buffer's capacity; the
   // buffer then holds only the header and the (unused) histograms
-  const bool sort = n_tiles > 1 && n_tiles <= capacity && !(dev >= 0 && dev < 64 && n_tiles <= resident[dev]);
+  const bool sort = n_tiles > 1 && n_tiles <= capacity && n_tiles > held;
   const int64_t lay = sort ? n_tiles : 0;
   char* w = (char*)work;
   int32_t* hdr = (int32_t*)w;
@@ -651,14 +655,19 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
 hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
                                const int32_t* d_sched, hipStream_t stream) {
   if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
-  static int resident_blocks = 0;  // blocks of this kernel the whole GPU keeps resident
+  // blocks of this kernel the whole GPU keeps resident (per device, queried once)
+  static std::atomic<int> resident[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int resident_blocks = (dev >= 0 && dev < 64) ? resident[dev].load(std::memory_order_relaxed) : 0;
   if (resident_blocks == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_batch_kernel, kThreads, 0);
     if (e != hipSuccess) return e;
     resident_blocks = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    if (dev >= 0 && dev < 64) resident[dev].store(resident_blocks, std::memory_order_relaxed);
   }
   const int64_t want = (n_tiles + 3) / 4;  // 4 waves per block
   const unsigned blocks = (unsigned)(want < resident_blocks ? want : resident_blocks);

@@ -312,6 +312,10 @@ salf_status salf_server_create(salf_context* ctx, const salf_server_opts* opts, 
     }
   }
   if (prev >= 0) (void)hipSetDevice(prev);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ++ctx->servers;
+  }
   s->worker = std::thread([s] { s->run(); });
   *out = s;
   return SALF_OK;
@@ -457,6 +461,10 @@ salf_status salf_server_destroy(salf_server* server) {
     if (s.stream) (void)hipStreamDestroy(s.stream);
   }
   if (prev >= 0) (void)hipSetDevice(prev);
+  {
+    std::lock_guard<std::mutex> lk(server->ctx->mu);
+    --server->ctx->servers;
+  }
   delete server;
   return SALF_OK;
 }

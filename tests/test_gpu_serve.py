@@ -108,3 +108,26 @@ def test_paper_field_scene_is_refused(salf):
     with pytest.raises(salf.SalfError, match="UNSUPPORTED"):
         srv.submit(sc, synth.pinhole(8, 8, 60.0, np.eye(3), (0, 0, -5)))
     srv.close()
+
+
+def test_context_outlives_its_servers(salf):
+    """salf_destroy refuses a context while a server created on it is alive."""
+    import ctypes as C
+    from paper_2507_18713_amd import _lib
+    lib = _lib.lib()
+    ctx = C.c_void_p()
+    assert lib.salf_create(dev().index or 0, C.byref(ctx)) == 0
+    op = _lib.ServerOpts()
+    op.max_batch, op.max_inflight = 4, 1
+    n = C.c_size_t()
+    assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == 0
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device=dev())
+    work = torch.empty(int(n.value), dtype=torch.uint8, device=dev())
+    op.d_pool, op.pool_bytes = pool.data_ptr(), pool.numel()
+    op.d_work, op.work_bytes = work.data_ptr(), work.numel()
+    srv = C.c_void_p()
+    assert lib.salf_server_create(ctx, C.byref(op), C.byref(srv)) == 0
+    assert lib.salf_destroy(ctx) == -6  # BUSY
+    assert b"server" in lib.salf_last_error()
+    assert lib.salf_server_destroy(srv) == 0
+    assert lib.salf_destroy(ctx) == 0
