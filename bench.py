@@ -519,6 +519,7 @@ def main():
         "event_ms_per_step": None if step_ms is None else round(step_ms, 4),
         "step": "camera frame and LiDAR sweep rendered concurrently on two streams",
         "scene_build_ms": round(build_ms, 3),
+        "dense_index_bytes": int(scene.index.numel()) if scene.index is not None else 0,
         "scene_generate_s": round(t_gen, 2),
         "kernel_source_hash": kernel_source_hash(),
     }

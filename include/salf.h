@@ -171,6 +171,28 @@ salf_status salf_scene_refresh(salf_context* ctx, int32_t scene_id, void* stream
 /* Statistics of a built scene.  Errors: NOT_FOUND. */
 salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out);
 
+/* Dense leaf index (optional; an acceleration of the octree walk of Sec. 3.2, same hits).  For
+ * every root cell whose finest voxel level L is in [1, max_level], a 2^L x 2^L x 2^L array (x
+ * fastest) of uint32 entries, one per level-L cell, names the octree region that holds that cell
+ * (a voxel, or an empty child): bits 0-3 the region's level, bits 4-31 its voxel + 1 (0: empty).
+ * Inside such a cell a ray then steps from region to region by one entry read instead of an
+ * octree descent per voxel; the reported hits and their intervals are the same.  The memory is
+ * caller-allocated: [int32 entry offset per root cell, -1 for cells without an index][entries].
+ *
+ * Exact bytes of the index of a built scene for `max_level` (copies the root grid to the host;
+ * blocking).  Errors: NOT_FOUND, INVALID_ARG (max_level outside [0, SALF_MAX_INDEX_LEVEL], a scene
+ * of 2^28 voxels or more), OUT_OF_MEMORY (more than 2^31 entries), DEVICE. */
+#define SALF_MAX_INDEX_LEVEL 6
+salf_status salf_scene_index_size(salf_context* ctx, int32_t scene_id, int32_t max_level, size_t* bytes);
+
+/* Build the index into d_index (256-byte aligned, >= salf_scene_index_size() bytes, caller-owned,
+ * not to be touched while the scene lives or until the index is replaced) on `stream` and block
+ * until it is built; later renders, traces and backward passes of the scene use it.  max_level 0
+ * drops the index.  Do not call it while work that reads the scene is in flight.  Errors: as
+ * salf_scene_index_size, plus INVALID_ARG (misaligned d_index), OUT_OF_MEMORY (bytes too small). */
+salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t max_level, void* d_index,
+                                   size_t bytes, void* stream);
+
 /* Forget a scene.  Its workspace and parameter buffers may be freed by the caller once the
  * work that used them has completed.  Errors: NOT_FOUND. */
 salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id);

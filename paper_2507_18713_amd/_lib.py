@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -
 FIELD_CORNER, FIELD_PAPER = 0, 1
 SCENE_PREACTIVATE = 1
 SCHEDULE_NONE, SCHEDULE_BUILD, SCHEDULE_REUSE = 0, 1, 2
+MAX_INDEX_LEVEL = 6  # SALF_MAX_INDEX_LEVEL
 PINHOLE, FISHEYE_EQUIDISTANT, LIDAR_SPINNING = 0, 1, 2
 
 
@@ -81,6 +82,8 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.POINTER(C.c_int32)]),
     "salf_scene_refresh": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "salf_scene_index_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "salf_scene_build_index": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "salf_scene_get_stats": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SceneStats)]),
     "salf_scene_destroy": (C.c_int32, [C.c_void_p, C.c_int32]),
     "salf_sensor_ray_count": (C.c_int32, [C.POINTER(Sensor), C.POINTER(C.c_int64)]),

@@ -68,15 +68,22 @@ def sensor_struct(s: dict) -> _lib.Sensor:
     return st
 
 
+# Root cells whose finest voxel level is at most this get a dense leaf index by default (16 KiB
+# per such cell at level 4).
+DEFAULT_INDEX_LEVEL = 4
+
+
 class Scene:
     """A scene registered with libsalf.  Holds the device tensors it borrows (parameters and the
     acceleration-structure workspace) for its lifetime."""
 
     def __init__(self, voxels: torch.Tensor, geo: torch.Tensor, rgb: Optional[torch.Tensor],
                  intensity: Optional[torch.Tensor], origin, root_size: float, root_dims, max_level: int,
-                 field: str = "corner", preactivate: bool = False):
+                 field: str = "corner", preactivate: bool = False, index_level: int = DEFAULT_INDEX_LEVEL):
         """preactivate (corner field): store activated corner values at build time; forward
-        renders read them (call refresh() after updating the parameters in place)."""
+        renders read them (call refresh() after updating the parameters in place).
+        index_level: root cells whose finest voxel level is at most this get a dense leaf index
+        (0: octree walk only); see build_index()."""
         dev = geo.device
         self.ctx = Context.get(dev)
         n = int(voxels.shape[0])
@@ -113,6 +120,24 @@ class Scene:
         self.preactivate = preactivate
         self.geo, self.rgb, self.intensity = geo, rgb, intensity
         self._voxels = voxels
+        self.index = None
+        self.index_level = 0
+        if index_level:
+            self.build_index(index_level)
+
+    def build_index(self, max_level: int):
+        """(Re)build the dense leaf index for root cells whose finest level is <= max_level (0 drops
+        it).  Blocks until built; call it when no render of this scene is in flight."""
+        nbytes = C.c_size_t()
+        call("salf_scene_index_size", self.ctx.handle, self.id, int(max_level), C.byref(nbytes))
+        if max_level == 0:
+            call("salf_scene_build_index", self.ctx.handle, self.id, 0, None, 0, _stream(self.device))
+            self.index, self.index_level = None, 0
+            return
+        buf = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        call("salf_scene_build_index", self.ctx.handle, self.id, int(max_level), _ptr(buf), int(buf.numel()),
+             _stream(self.device))
+        self.index, self.index_level = buf, int(max_level)
 
     def refresh(self):
         """Re-derive the stored activated corner values from the parameters (pre-activated scenes)."""
@@ -120,7 +145,8 @@ class Scene:
 
     @classmethod
     def from_data(cls, data, device="cuda", field: str = "corner", rgb: bool = True, intensity: bool = True,
-                  requires_grad: bool = False, preactivate: bool = False) -> "Scene":
+                  requires_grad: bool = False, preactivate: bool = False,
+                  index_level: int = None) -> "Scene":
         """Upload a scene given as numpy arrays (attributes origin, root_size, root_dims, max_level,
         voxels [N,4] int32, z_geo [N,8], z_rgb [N,3,8], z_int [N,8] or None)."""
         dev = torch.device(device)
@@ -137,7 +163,7 @@ class Scene:
                 if t is not None:
                     t.requires_grad_(True)
         return cls(vox, geo, col, ity, data.origin, data.root_size, data.root_dims, data.max_level, field,
-                   preactivate)
+                   preactivate, DEFAULT_INDEX_LEVEL if index_level is None else index_level)
 
     def stats(self) -> dict:
         s = _lib.SceneStats()

@@ -200,6 +200,44 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
 
 }  // namespace
 
+namespace {
+// Entry offsets of the dense leaf indexes of a scene's root cells whose finest voxel level is in
+// [1, max_level] (-1 for the other cells), from the built root grid, and their entry count.
+salf_status index_plan(salf_context* ctx, const Scene& sc, int32_t max_level, std::vector<int32_t>* boff,
+                       int64_t* entries) {
+  const int64_t n_root = sc.layout.n_root;
+  std::vector<int32_t> root((size_t)n_root), lmax((size_t)n_root);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", ctx->device);
+  salf_status st;
+  if ((st = check_hip(hipMemcpy(root.data(), sc.view.root, n_root * 4, hipMemcpyDeviceToHost), "copy root grid")))
+    return st;
+  if ((st = check_hip(hipMemcpy(lmax.data(), sc.view.lmax, n_root * 4, hipMemcpyDeviceToHost), "copy levels")))
+    return st;
+  boff->assign((size_t)n_root, -1);
+  int64_t total = 0;
+  for (int64_t i = 0; i < n_root; ++i) {
+    if (root[i] < 0 || lmax[i] < 1 || lmax[i] > max_level) continue;
+    (*boff)[i] = (int32_t)total;
+    total += (int64_t)1 << (3 * lmax[i]);
+    if (total > INT32_MAX) return set_error(SALF_ERR_OUT_OF_MEMORY, "dense leaf index exceeds 2^31 entries");
+  }
+  *entries = total;
+  return SALF_OK;
+}
+
+size_t index_bytes(int64_t n_root, int64_t entries) { return ((size_t)n_root * 4 + 255) / 256 * 256 + (size_t)entries * 4; }
+
+salf_status check_index_args(salf_context* ctx, int32_t scene_id, int32_t max_level, Scene** sc) {
+  salf_status st = find_scene(ctx, scene_id, sc);
+  if (st) return st;
+  if (max_level < 0 || max_level > SALF_MAX_INDEX_LEVEL)
+    return set_error(SALF_ERR_INVALID_ARG, "index level %d outside [0, %d]", max_level, SALF_MAX_INDEX_LEVEL);
+  if ((*sc)->n >= ((int64_t)1 << 28)) return set_error(SALF_ERR_INVALID_ARG, "a dense leaf index holds < 2^28 voxels");
+  return SALF_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t salf_abi_version(void) { return SALF_ABI_VERSION; }
@@ -293,6 +331,8 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
   v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
   v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
+  v.boff = nullptr;
+  v.cidx = nullptr;
   v.act_geo = v.act_rgb = v.act_int = nullptr;
   if (desc->flags & SALF_SCENE_PREACTIVATE) {
     v.act_geo = (const float*)((char*)d_workspace + L.act_geo_off);
@@ -349,6 +389,51 @@ salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene
   out->n_root_cells = sc->layout.n_root;
   out->n_occupied_roots = sc->counters.n_occupied;
   out->workspace_bytes = sc->layout.total;
+  return SALF_OK;
+}
+
+salf_status salf_scene_index_size(salf_context* ctx, int32_t scene_id, int32_t max_level, size_t* bytes) {
+  Scene* sc = nullptr;
+  salf_status st = check_index_args(ctx, scene_id, max_level, &sc);
+  if (st) return st;
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  std::vector<int32_t> boff;
+  int64_t entries = 0;
+  if ((st = index_plan(ctx, *sc, max_level, &boff, &entries))) return st;
+  *bytes = index_bytes(sc->layout.n_root, entries);
+  return SALF_OK;
+}
+
+salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t max_level, void* d_index,
+                                   size_t bytes, void* stream) {
+  Scene* sc = nullptr;
+  salf_status st = check_index_args(ctx, scene_id, max_level, &sc);
+  if (st) return st;
+  if (max_level == 0) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    sc->view.boff = nullptr;
+    sc->view.cidx = nullptr;
+    return SALF_OK;
+  }
+  if (!d_index || ((uintptr_t)d_index & 255u)) return set_error(SALF_ERR_INVALID_ARG, "index must be 256-byte aligned");
+  std::vector<int32_t> boff;
+  int64_t entries = 0;
+  if ((st = index_plan(ctx, *sc, max_level, &boff, &entries))) return st;
+  const int64_t n_root = sc->layout.n_root;
+  const size_t need = index_bytes(n_root, entries);
+  if (bytes < need) return set_error(SALF_ERR_OUT_OF_MEMORY, "index has %zu bytes, it needs %zu", bytes, need);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", ctx->device);
+  const hipStream_t s = (hipStream_t)stream;
+  int32_t* d_boff = (int32_t*)d_index;
+  uint32_t* d_entries = (uint32_t*)((char*)d_index + index_bytes(n_root, 0));
+  if ((st = check_hip(hipMemcpyAsync(d_boff, boff.data(), n_root * 4, hipMemcpyHostToDevice, s), "copy index offsets")))
+    return st;
+  if ((st = check_hip(launch_index_fill(sc->view, n_root, d_boff, d_entries, s), "index launch"))) return st;
+  if ((st = check_hip(hipStreamSynchronize(s), "index build"))) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  sc->view.boff = d_boff;
+  sc->view.cidx = d_entries;
   return SALF_OK;
 }
 

@@ -35,6 +35,9 @@ struct SceneView {
   const uint8_t* skip;   // [Dz][Dy][Dx] Chebyshev distance (in root cells, capped) to the nearest
                          // occupied root cell; 0 = occupied.  Null: no empty-space skipping.
   const int32_t* lmax;   // [Dz][Dy][Dx] finest voxel level in each root cell (tile cost estimates)
+  const int32_t* boff;   // [Dz][Dy][Dx] first entry of each root cell's dense leaf index, or -1;
+                         // null: no index
+  const uint32_t* cidx;  // dense leaf indexes (see kIdx* below)
   const float* act_geo;  // activated corner values (pre-activated corner scenes), same layouts as
   const float* act_rgb;  // geo / rgb / inten; null otherwise
   const float* act_int;
@@ -236,6 +239,98 @@ __device__ __forceinline__ float sample_u(float rel, float stp, float fk, float 
   return __builtin_amdgcn_fmed3f(fmaf(fk, stp, rel) * sc, 0.0f, 1.0f);
 }
 
+// Dense leaf index of a root cell whose finest voxel level is L: 2^L x 2^L x 2^L entries (x
+// fastest), one per cell of level L, each naming the region of the cell's octree that holds it:
+// bits 0-3 the region's level (1..L), bits 4-31 its voxel + 1 (0: an empty region).
+constexpr int kIdxLevelBits = 4;
+constexpr uint32_t kIdxLevelMask = 15u;
+
+// Index of the level-L cell of one axis (edge 2^sh finest cells, root cell min corner lo) whose
+// half-open slab holds tc under the rule, and the crossing where the ray leaves it; the same
+// predicate as the octree descent's mid-plane tests (monotone crossings), found from a position
+// guess corrected against the crossings.
+__device__ __forceinline__ void locate_fine(const RayFrame& f, int a, float tc, int32_t lo, int sh, int R, int& c,
+                                            float& nxt) {
+  const float og = f.og[a], inv = f.inv[a];
+  if (f.par & (1 << a)) {
+    c = ((int32_t)floorf(og) - lo) >> sh;
+    c = c < 0 ? 0 : (c >= R ? R - 1 : c);
+    nxt = INFINITY;
+    return;
+  }
+  c = ((int32_t)floorf(og + tc * f.dg[a]) - lo) >> sh;
+  c = c < 0 ? 0 : (c >= R ? R - 1 : c);
+  if (inv > 0.0f) {
+    while (c > 0 && plane_t((float)(lo + (c << sh)), og, inv) > tc) --c;
+    while (c < R - 1 && plane_t((float)(lo + ((c + 1) << sh)), og, inv) <= tc) ++c;
+    nxt = plane_t((float)(lo + ((c + 1) << sh)), og, inv);
+  } else {
+    while (c < R - 1 && plane_t((float)(lo + ((c + 1) << sh)), og, inv) > tc) ++c;
+    while (c > 0 && plane_t((float)(lo + (c << sh)), og, inv) <= tc) --c;
+    nxt = plane_t((float)(lo + (c << sh)), og, inv);
+  }
+}
+
+// Step one axis's level-L cell index past every crossing <= tc (the index stays in [0, R)).
+__device__ __forceinline__ void step_fine(const RayFrame& f, int a, float tc, int32_t lo, int sh, int R, int& c,
+                                          float& nxt) {
+  if (f.par & (1 << a)) return;
+  const float og = f.og[a], inv = f.inv[a];
+  if (inv > 0.0f) {
+    while (nxt <= tc && c < R - 1) {
+      ++c;
+      nxt = plane_t((float)(lo + ((c + 1) << sh)), og, inv);
+    }
+  } else {
+    while (nxt <= tc && c > 0) {
+      --c;
+      nxt = plane_t((float)(lo + (c << sh)), og, inv);
+    }
+  }
+}
+
+// The leaf loop of a root cell with a dense leaf index: each pass reads the entry of the level-L
+// cell holding tc, reports the region if it is a voxel, moves tc to the region's exit crossing and
+// steps the per-axis cell indices past it.  Same passes as the octree walk, minus its descents and
+// pops.  False if visit asked to stop.
+template <typename Visit>
+__device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f, const int32_t lo[3], int L,
+                                           const uint32_t* idx, float tc, float cell_end, int& budget, Hit& h,
+                                           Visit&& visit) {
+  if (!(tc < cell_end)) return true;
+  const int sh = s.K - L;
+  const int R = 1 << L;
+  int c0, c1, c2;
+  float n0, n1, n2;
+  locate_fine(f, 0, tc, lo[0], sh, R, c0, n0);
+  locate_fine(f, 1, tc, lo[1], sh, R, c1, n1);
+  locate_fine(f, 2, tc, lo[2], sh, R, c2, n2);
+  while (budget-- > 0) {
+    const uint32_t e = idx[(((c2 << L) + c1) << L) + c0];
+    const int rs = L - (int)(e & kIdxLevelMask);  // log2 of the region's edge in level-L cells
+    const int32_t size = (1 << (rs + sh));
+    h.lo[0] = lo[0] + ((c0 >> rs) << (rs + sh));
+    h.lo[1] = lo[1] + ((c1 >> rs) << (rs + sh));
+    h.lo[2] = lo[2] + ((c2 >> rs) << (rs + sh));
+    // a level-L region's exit planes are the ones the per-axis crossings already hold
+    const float to = rs == 0 ? fminf(fminf(n0, n1), fminf(n2, f.t_far)) : box_exit(f, h.lo, size);
+    if (e >> kIdxLevelBits) {
+      h.voxel = (int32_t)(e >> kIdxLevelBits) - 1;
+      h.size = size;
+      h.t_in = tc;
+      h.t_out = to;
+      if (!visit(h)) return false;
+    }
+    if (!(to > tc)) return true;  // cannot happen under the rule; guards against a stall
+    tc = to;
+    if (!(tc < cell_end)) return true;
+    step_fine(f, 0, tc, lo[0], sh, R, c0, n0);
+    step_fine(f, 1, tc, lo[1], sh, R, c1, n1);
+    step_fine(f, 2, tc, lo[2], sh, R, c2, n2);
+  }
+  return true;
+}
+
 // Front-to-back walk over the voxels a ray hits: calls visit(hit) for each, in increasing t_in,
 // until visit returns false.  Each voxel is reported exactly once with the rule's interval.
 //
@@ -279,17 +374,21 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
     float t_next = cell_exit;
     if (code >= 0) {
       // octree of this root cell, entered where the ray meets the bounds of its voxels
-      int depth = 0;
-      int32_t size = N0;
       int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
-      stk[0] = code;
-      const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
-      int4 c0 = np[0], c1 = np[1];
+      const int32_t bo = s.boff != nullptr ? s.boff[lin] : -1;
       float b_in, b_out;
       const bool meets = node_bounds(f, lo, s.nbox[code], b_in, b_out);
       float tc = fmaxf(t, b_in);
       const float cell_end = fminf(cell_exit, b_out);
       if (!meets) tc = cell_end;
+      if (bo >= 0) {
+        if (!index_walk(s, f, lo, s.lmax[lin], s.cidx + bo, tc, cell_end, budget, h, visit)) return;
+      } else {
+      int depth = 0;
+      int32_t size = N0;
+      stk[0] = code;
+      const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
+      int4 c0 = np[0], c1 = np[1];
       while (tc < cell_end && budget-- > 0) {
         // (1) descend to the leaf holding tc
         int32_t clo[3], half, child;
@@ -363,6 +462,7 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
           c0 = np[0];
           c1 = np[1];
         }
+      }
       }
     } else if (is_leaf_code(code)) {
       // a level-0 voxel fills the root cell: it holds t, so its interval is [t, cell_exit]

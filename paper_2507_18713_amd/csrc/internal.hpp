@@ -43,6 +43,10 @@ struct BuildCounters {
 hipError_t launch_activate(const float* geo, const float* rgb, const float* inten, int64_t n_voxels, float* act_geo,
                            float* act_rgb, float* act_int, hipStream_t stream);
 
+// Dense leaf indexes of a built scene: boff[cell] is the first entry of the cell's index or -1.
+hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
+                             hipStream_t stream);
+
 hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n_voxels, const int32_t* voxels,
                               const SceneLayout& L, void* ws, hipStream_t stream);
 

@@ -396,6 +396,39 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
 }
 
 namespace {
+// Dense leaf index of every root cell with boff[cell] >= 0 (one workgroup per cell): each entry
+// descends the cell's octree to the region that holds its level-L cell (the first child on the
+// way that is a voxel or empty) and records that region's level and voxel.
+__global__ void index_fill_kernel(const int32_t* root, const int32_t* nodes, const int32_t* lmax,
+                                  const int32_t* boff, int64_t cell0, uint32_t* entries) {
+  const int64_t cell = cell0 + blockIdx.x;
+  const int32_t off = boff[cell];
+  if (off < 0) return;
+  const int L = lmax[cell];
+  const int32_t code = root[cell];
+  const int32_t n = 1 << (3 * L);
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int32_t x = i & ((1 << L) - 1), y = (i >> L) & ((1 << L) - 1), z = i >> (2 * L);
+    int32_t node = code;
+    uint32_t e = (uint32_t)L;  // a malformed tree (an internal node at level L) reads as empty
+    for (int d = 0; d < L; ++d) {
+      const int b = L - 1 - d;
+      const int c8 = ((x >> b) & 1) | (((y >> b) & 1) << 1) | (((z >> b) & 1) << 2);
+      const int32_t ch = nodes[(int64_t)node * 8 + c8];
+      if (is_leaf_code(ch)) {
+        e = ((uint32_t)(leaf_voxel(ch) + 1) << kIdxLevelBits) | (uint32_t)(d + 1);
+        break;
+      }
+      if (ch < 0) {
+        e = (uint32_t)(d + 1);
+        break;
+      }
+      node = ch;
+    }
+    entries[(int64_t)off + i] = e;
+  }
+}
+
 // Corner activations for pre-activated scenes (the same functions the render kernels apply).
 __global__ void activate_kernel(const float* src, float* dst, int64_t n, int softplus) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -411,6 +444,15 @@ hipError_t launch_activate(const float* geo, const float* rgb, const float* inte
   activate_kernel<<<grid(n * 8), T, 0, stream>>>(geo, act_geo, n * 8, 1);
   if (rgb) activate_kernel<<<grid(n * 24), T, 0, stream>>>(rgb, act_rgb, n * 24, 0);
   if (inten) activate_kernel<<<grid(n * 8), T, 0, stream>>>(inten, act_int, n * 8, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
+                             hipStream_t stream) {
+  for (int64_t c0 = 0; c0 < n_root; c0 += (int64_t)1 << 30) {
+    const int64_t m = n_root - c0 < ((int64_t)1 << 30) ? n_root - c0 : ((int64_t)1 << 30);
+    index_fill_kernel<<<(unsigned)m, 256, 0, stream>>>(v.root, v.nodes, v.lmax, boff, c0, entries);
+  }
   return hipGetLastError();
 }
 

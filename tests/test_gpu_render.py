@@ -7,6 +7,8 @@ as an oracle input.
 """
 import math
 
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -91,11 +93,13 @@ def test_tiny_scene_all_rays(salf, S):
         assert torch.equal(lin[k], got[k]), k
 
 
-@pytest.mark.parametrize("seed,K", [(31, 1), (32, 2), (33, 3)])
-def test_adaptive_scenes_random_rays(salf, seed, K):
+# index: the dense-leaf-index level of the scene (0: octree walk only; 2 with K = 3 mixes the two
+# walks, since cells whose finest level is 3 keep the octree)
+@pytest.mark.parametrize("seed,K,index", [(31, 1, 4), (32, 2, 4), (33, 3, 4), (32, 2, 0), (33, 3, 0), (33, 3, 2)])
+def test_adaptive_scenes_random_rays(salf, seed, K, index):
     data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=K)
     ps = oracle.prepare(data)
-    scene = salf.Scene.from_data(data, device=dev())
+    scene = salf.Scene.from_data(data, device=dev(), index_level=index)
     lo, hi = data.origin, data.origin + data.root_dims * data.root_size
     o, d = synth.random_rays(seed, 700, lo, hi)
     # axis-parallel rays, rays on faces and rays from inside a voxel exercise the rule's corners
@@ -108,6 +112,67 @@ def test_adaptive_scenes_random_rays(salf, seed, K):
     check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(background=bg)))
     st = scene.stats()
     assert st["n_voxels"] == data.n and st["n_nodes"] > 0
+
+
+def test_dense_index_changes_nothing(salf):
+    """Renders, hit lists and gradients are the same bits with the dense leaf index at every level
+    (cells above the level keep the octree walk) and without it."""
+    data = synth.random_scene(35, root_dims=(4, 3, 3), max_level=4)
+    scene = salf.Scene.from_data(data, device=dev(), index_level=0, requires_grad=True)
+    lo, hi = data.origin, data.origin + data.root_dims * data.root_size
+    o, d = synth.random_rays(36, 6000, lo, hi)
+    d[:6] = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0], [0, 0, -1]], F32)
+    o[6:12] = (data.origin + np.array([1.0, 1.0, 1.0]) * data.root_size).astype(F32)
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+
+    def run():
+        r = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=outs, image_width=50)
+        h = salf.trace_hits(scene, to_dev(o), to_dev(d), max_hits=512)
+        grads = {"rgb": torch.ones_like(r["rgb"]), "depth": torch.full_like(r["depth"], 0.5),
+                 "intensity": torch.ones_like(r["intensity"])}
+        g = salf.render_backward(scene, r, grads, o=to_dev(o), d=to_dev(d), image_width=50)
+        return r, h, g
+
+    r0, h0, g0 = run()
+    assert int(r0["n_hits"].sum()) > 12000 and g0[0].abs().sum() > 0
+    for level in (1, 2, 3, 4, 6):
+        scene.build_index(level)
+        r, h, g = run()
+        for k in outs:
+            assert torch.equal(r[k], r0[k]), (level, k)
+        for a, b in zip(h, h0):  # entries past a ray's count are NaN on both sides
+            assert torch.equal(a, b) or bool(torch.all((a == b) | (torch.isnan(a) & torch.isnan(b)))), level
+        for a, b in zip(g, g0):  # same hits; only the order of the gradient atomics may differ
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6), level
+    scene.build_index(0)
+    assert scene.index is None
+
+
+def test_dense_index_errors(salf):
+    from paper_2507_18713_amd._lib import MAX_INDEX_LEVEL, call
+    data = synth.random_scene(37, root_dims=(3, 3, 2), max_level=3)
+    scene = salf.Scene.from_data(data, device=dev(), index_level=0)
+    nbytes = ctypes.c_size_t()
+    for bad in (-1, MAX_INDEX_LEVEL + 1):
+        with pytest.raises(salf.SalfError, match="index level"):
+            call("salf_scene_index_size", scene.ctx.handle, scene.id, bad, ctypes.byref(nbytes))
+    call("salf_scene_index_size", scene.ctx.handle, scene.id, 3, ctypes.byref(nbytes))
+    need = int(nbytes.value)
+    assert need >= 256
+    buf = torch.empty(need + 256, dtype=torch.uint8, device=dev())
+    stream = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(salf.SalfError, match="needs"):
+        call("salf_scene_build_index", scene.ctx.handle, scene.id, 3, buf.data_ptr(), need - 4, stream)
+    with pytest.raises(salf.SalfError, match="aligned"):
+        call("salf_scene_build_index", scene.ctx.handle, scene.id, 3, buf.data_ptr() + 4, need, stream)
+    with pytest.raises(salf.SalfError, match="no scene"):
+        call("salf_scene_index_size", scene.ctx.handle, 999, 3, ctypes.byref(nbytes))
+    # a failed build leaves the scene without an index; a good one renders as before
+    o, d = synth.random_rays(38, 300, data.origin, data.origin + data.root_dims * data.root_size)
+    ref = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    call("salf_scene_build_index", scene.ctx.handle, scene.id, 3, buf.data_ptr(), need, stream)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    assert torch.equal(got["rgb"], ref["rgb"]) and torch.equal(got["n_hits"], ref["n_hits"])
 
 
 def test_paper_field_forward(salf):
