@@ -331,6 +331,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.skip = (const uint8_t*)((char*)d_workspace + L.skip_off);
   v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
   v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
+  v.rbox = (const uint2*)((char*)d_workspace + L.rbox_off);
   v.boff = nullptr;
   v.cidx = nullptr;
   v.act_geo = v.act_rgb = v.act_int = nullptr;

@@ -34,7 +34,8 @@ struct SceneView {
   const float* inten;    // [N][8] or null
   const uint8_t* skip;   // [Dz][Dy][Dx] Chebyshev distance (in root cells, capped) to the nearest
                          // occupied root cell; 0 = occupied.  Null: no empty-space skipping.
-  const int32_t* lmax;   // [Dz][Dy][Dx] finest voxel level in each root cell (tile cost estimates)
+  const int32_t* lmax;   // [Dz][Dy][Dx] finest voxel level in each root cell
+  const uint2* rbox;     // [Dz][Dy][Dx] nbox of each root cell's node (zero for other cells)
   const int32_t* boff;   // [Dz][Dy][Dx] first entry of each root cell's dense leaf index, or -1;
                          // null: no index
   const uint32_t* cidx;  // dense leaf indexes (see kIdx* below)
@@ -305,8 +306,8 @@ __device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f
   locate_fine(f, 0, tc, lo[0], sh, R, c0, n0);
   locate_fine(f, 1, tc, lo[1], sh, R, c1, n1);
   locate_fine(f, 2, tc, lo[2], sh, R, c2, n2);
+  uint32_t e = idx[(((c2 << L) + c1) << L) + c0];
   while (budget-- > 0) {
-    const uint32_t e = idx[(((c2 << L) + c1) << L) + c0];
     const int rs = L - (int)(e & kIdxLevelMask);  // log2 of the region's edge in level-L cells
     const int32_t size = (1 << (rs + sh));
     h.lo[0] = lo[0] + ((c0 >> rs) << (rs + sh));
@@ -314,6 +315,15 @@ __device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f
     h.lo[2] = lo[2] + ((c2 >> rs) << (rs + sh));
     // a level-L region's exit planes are the ones the per-axis crossings already hold
     const float to = rs == 0 ? fminf(fminf(n0, n1), fminf(n2, f.t_far)) : box_exit(f, h.lo, size);
+    // step to the next region and start reading its entry before this one is shaded
+    const bool more = to > tc && to < cell_end;  // (to > tc always holds under the rule)
+    uint32_t e_next = 0;
+    if (more) {
+      step_fine(f, 0, to, lo[0], sh, R, c0, n0);
+      step_fine(f, 1, to, lo[1], sh, R, c1, n1);
+      step_fine(f, 2, to, lo[2], sh, R, c2, n2);
+      e_next = idx[(((c2 << L) + c1) << L) + c0];
+    }
     if (e >> kIdxLevelBits) {
       h.voxel = (int32_t)(e >> kIdxLevelBits) - 1;
       h.size = size;
@@ -321,12 +331,9 @@ __device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f
       h.t_out = to;
       if (!visit(h)) return false;
     }
-    if (!(to > tc)) return true;  // cannot happen under the rule; guards against a stall
+    if (!more) return true;
     tc = to;
-    if (!(tc < cell_end)) return true;
-    step_fine(f, 0, tc, lo[0], sh, R, c0, n0);
-    step_fine(f, 1, tc, lo[1], sh, R, c1, n1);
-    step_fine(f, 2, tc, lo[2], sh, R, c2, n2);
+    e = e_next;
   }
   return true;
 }
@@ -370,14 +377,17 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
   while (budget-- > 0) {
     const float cell_exit = fminf(fminf(ax.nxt, ay.nxt), fminf(az.nxt, t_exit));
     const int64_t lin = ((int64_t)az.k * s.dims[1] + ay.k) * s.dims[0] + ax.k;
+    // the cell's code, voxel bounds, skip distance and index offset, read together
     const int32_t code = s.root[lin];
+    const uint2 rb = s.rbox[lin];
+    const int dskip = s.skip != nullptr ? s.skip[lin] : 0;
+    const int32_t bo = s.boff != nullptr ? s.boff[lin] : -1;
     float t_next = cell_exit;
     if (code >= 0) {
       // octree of this root cell, entered where the ray meets the bounds of its voxels
       int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
-      const int32_t bo = s.boff != nullptr ? s.boff[lin] : -1;
       float b_in, b_out;
-      const bool meets = node_bounds(f, lo, s.nbox[code], b_in, b_out);
+      const bool meets = node_bounds(f, lo, rb, b_in, b_out);
       float tc = fmaxf(t, b_in);
       const float cell_end = fminf(cell_exit, b_out);
       if (!meets) tc = cell_end;
@@ -474,11 +484,9 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
       h.t_in = t;
       h.t_out = cell_exit;
       if (!visit(h)) return;
-    } else if (s.skip != nullptr) {
-      const int d = s.skip[lin];
-      if (d > 1)  // leave the empty cube of radius d - 1 around this cell
-        t_next = fminf(fminf(cube_exit<0>(f, s, ax, d), cube_exit<1>(f, s, ay, d)),
-                       fminf(cube_exit<2>(f, s, az, d), t_exit));
+    } else if (dskip > 1) {  // leave the empty cube of radius dskip - 1 around this cell
+      t_next = fminf(fminf(cube_exit<0>(f, s, ax, dskip), cube_exit<1>(f, s, ay, dskip)),
+                     fminf(cube_exit<2>(f, s, az, dskip), t_exit));
     }
     if (!(t_next < t_exit)) return;
     t = t_next;
@@ -523,7 +531,7 @@ __device__ inline float root_cost(const SceneView& s, const RayFrame& f, float l
     if (code >= 0) {
       const int32_t lo[3] = {ax.k << K, ay.k << K, az.k << K};
       float b_in, b_out;
-      if (node_bounds(f, lo, s.nbox[code], b_in, b_out)) {
+      if (node_bounds(f, lo, s.rbox[lin], b_in, b_out)) {
         const float l = fminf(b_out, cell_exit) - fmaxf(b_in, t);
         if (l > 0.0f) len += l * (float)(1 << s.lmax[lin]);
       }

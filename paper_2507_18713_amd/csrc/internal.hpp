@@ -17,7 +17,7 @@ namespace salf {
 salf_status set_error(salf_status code, const char* fmt, ...);
 salf_status check_hip(hipError_t e, const char* what);
 
-// ---- scene workspace layout: [root grid][skip grid][nodes][node bounds][bounds scratch][hash keys]
+// ---- scene workspace layout: [root grid][skip grid][levels][root bounds][nodes][node bounds][bounds scratch][hash keys]
 //      [hash values][2 temp grids][counters][activated corner values, pre-activated scenes only]
 struct SceneLayout {
   int64_t n_root;        // root cells
@@ -26,6 +26,7 @@ struct SceneLayout {
   size_t root_off, skip_off, nodes_off, nbox_off, box_tmp_off, hkeys_off, hvals_off, tmp_off, counters_off;
   size_t order_off;  // node-numbering temporaries (0 when the scene can have no nodes)
   size_t lmax_off;   // finest voxel level per root cell
+  size_t rbox_off;   // bounds of each root cell's voxels (uint2 per cell, zero for cells without a node)
   size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
   size_t total;
 };

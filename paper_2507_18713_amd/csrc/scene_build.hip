@@ -308,6 +308,15 @@ __global__ void box_pack(BuildArgs a) {
   a.nbox[id] = make_uint2(lo, hi);
 }
 
+// Bounds of each root cell's voxels (its root node's), indexed by cell, so that a walk can read
+// them together with the cell's code.
+__global__ void root_box_kernel(const int32_t* root, const uint2* nbox, uint2* rbox, int64_t n_root) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_root; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = root[i];
+    rbox[i] = c >= 0 ? nbox[c] : make_uint2(0u, 0u);
+  }
+}
+
 __global__ void count_roots(const int32_t* root, int64_t n, BuildCounters* c) {
   int32_t mine = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -363,6 +372,8 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   off = up(off + (size_t)n_root);
   L->lmax_off = off;
   off = up(off + (size_t)n_root * 4);
+  L->rbox_off = off;
+  off = up(off + (size_t)n_root * 8);
   L->nodes_off = off;
   off = up(off + (size_t)node_cap * 32);
   L->nbox_off = off;
@@ -496,6 +507,8 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   }
   if (n > 0) link_kernel<<<blocks_for(n, T), T, 0, stream>>>(a);
   box_pack<<<(unsigned)((L.hash_cap + T - 1) / T), T, 0, stream>>>(a);
+  root_box_kernel<<<blocks_for(L.n_root, T) > 8192 ? 8192 : blocks_for(L.n_root, T), T, 0, stream>>>(
+      a.root, a.nbox, (uint2*)(base + L.rbox_off), L.n_root);
   {
     uint8_t* skip = (uint8_t*)(base + L.skip_off);
     uint8_t* t0 = (uint8_t*)(base + L.tmp_off);
