@@ -84,11 +84,12 @@ __host__ __device__ inline int64_t tile_count(const RenderParams& p) {
 size_t tile_work_bytes(int64_t n_tiles);
 hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream);
 
-// Tile shape of a wave: 8 x 8 pixels for cameras (and explicit rays with an image layout), 32
-// columns x 2 beams for a spinning LiDAR, whose neighbouring beams differ far more in path length
-// than neighbouring columns do.
+// Tile shape of a wave: 16 x 4 pixels for a pinhole camera, whose rows near the horizon differ more
+// in path length (the distance at which they meet the ground) than its columns do; 32 columns x 2
+// beams for a spinning LiDAR, for the same reason; 8 x 8 for a fisheye camera and for explicit
+// rays with an image layout.
 inline void set_tiling(RenderParams* p, int sensor_model) {
-  p->tw_log2 = sensor_model == SALF_LIDAR_SPINNING ? 5 : 3;
+  p->tw_log2 = sensor_model == SALF_LIDAR_SPINNING ? 5 : (sensor_model == SALF_PINHOLE ? 4 : 3);
   const int tw = 1 << p->tw_log2, th = 64 >> p->tw_log2;
   p->tiles_x = (p->img_w + tw - 1) / tw;
   p->tiles_y = (p->img_h + th - 1) / th;
