@@ -107,9 +107,10 @@ struct BatchItem {
 };
 // d_items: device array of n_items requests sorted by tile_begin (the first begins at 0);
 // d_counter: a zeroed device word the waves pull tiles from; d_sched: a batch schedule built by
-// launch_batch_schedule for these items (or null: tiles in request order).
+// launch_batch_schedule for these items (or null: tiles in request order); variants: bit v set
+// when some request has variant v.
 hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
-                               const int32_t* d_sched, hipStream_t stream);
+                               const int32_t* d_sched, uint32_t variants, hipStream_t stream);
 // Heaviest-first schedule of the n_tiles global tiles of a batch, in a buffer of
 // tile_work_bytes(kBatchScheduleTiles) bytes.  Larger batches (more than about four 1920x1080
 // frames) keep request order: their tail is short next to their length, and interleaving the

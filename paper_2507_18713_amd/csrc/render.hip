@@ -198,8 +198,13 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   if (out.n_hits) out.n_hits[ray] = acc.n;
 }
 
+// At most 168 VGPRs, so that three waves fit each SIMD: the heavier variants (raw logits, colour
+// and intensity) would otherwise take a few more registers and drop to two waves, which costs far
+// more than the few spills the cap causes.
+#define SALF_RENDER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3)))
+
 template <int FIELD, bool RGB, bool INT>
-__global__ __launch_bounds__(kThreads) void render_kernel(RenderParams p) {
+__global__ __launch_bounds__(kThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
   render_wave<FIELD, RGB, INT>(p, scheduled_tile(p, w), stk + threadIdx.x);
@@ -313,7 +318,13 @@ __global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint32_t* ke
 // whose waves pull global tile numbers from a counter until every tile of every request is done
 // (each wave's exit condition is that counter passing the tile count).  The request of a tile is
 // found by binary search over the requests' first tiles; its shading variant is uniform per wave.
-__global__ __launch_bounds__(kThreads) void render_batch_kernel(const BatchItem* items, int32_t n_items,
+// MASK (bit v: variant v) names the variants the kernel is built for: each one inlined adds to the
+// registers the whole kernel holds, so launches whose requests use fewer variants get a kernel
+// with only those.  The kernel for pre-activated colour and intensity requests (cameras and LiDARs
+// together, the common serving mix) is capped at three waves per SIMD: it would take 194 VGPRs
+// (two waves); the cap spills 18 of them and is faster by about 14% in the serving loop.
+template <uint32_t MASK>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MASK == 0x60u ? 3 : 1))) void render_batch_kernel(const BatchItem* items, int32_t n_items,
                                                                 int64_t n_tiles, uint32_t* counter,
                                                                 const int32_t* sched) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
@@ -331,16 +342,15 @@ __global__ __launch_bounds__(kThreads) void render_batch_kernel(const BatchItem*
     }
     const BatchItem& b = items[find_item(items, n_items, tile)];
     const int64_t w = tile - b.tile_begin;
-    switch (b.variant) {
-      case 0: render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x); break;
-      case 1: render_wave<SALF_FIELD_CORNER, true, false>(b.p, w, stk + threadIdx.x); break;
-      case 2: render_wave<SALF_FIELD_CORNER, false, true>(b.p, w, stk + threadIdx.x); break;
-      case 3: render_wave<SALF_FIELD_CORNER, true, true>(b.p, w, stk + threadIdx.x); break;
-      case 4: render_wave<kFieldCornerActivated, false, false>(b.p, w, stk + threadIdx.x); break;
-      case 5: render_wave<kFieldCornerActivated, true, false>(b.p, w, stk + threadIdx.x); break;
-      case 6: render_wave<kFieldCornerActivated, false, true>(b.p, w, stk + threadIdx.x); break;
-      default: render_wave<kFieldCornerActivated, true, true>(b.p, w, stk + threadIdx.x); break;
-    }
+    const int v = b.variant;
+    if constexpr ((MASK & 0x01u) != 0) if (v == 0) render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x02u) != 0) if (v == 1) render_wave<SALF_FIELD_CORNER, true, false>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x04u) != 0) if (v == 2) render_wave<SALF_FIELD_CORNER, false, true>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x08u) != 0) if (v == 3) render_wave<SALF_FIELD_CORNER, true, true>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x10u) != 0) if (v == 4) render_wave<kFieldCornerActivated, false, false>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x20u) != 0) if (v == 5) render_wave<kFieldCornerActivated, true, false>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x40u) != 0) if (v == 6) render_wave<kFieldCornerActivated, false, true>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x80u) != 0) if (v == 7) render_wave<kFieldCornerActivated, true, true>(b.p, w, stk + threadIdx.x);
   }
 }
 
@@ -652,27 +662,44 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
   return launch_field<SALF_FIELD_CORNER>(p, blocks, stream);
 }
 
-hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
-                               const int32_t* d_sched, hipStream_t stream) {
-  if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
-  // blocks of this kernel the whole GPU keeps resident (per device, queried once)
-  static std::atomic<int> resident[64];
+namespace {
+// Kernels of the batched launch, each built for a set of variants: pre-activated colour-only and
+// intensity-only requests (cameras and LiDARs), every pre-activated variant, every variant.
+constexpr uint32_t kBatchMasks[3] = {0x60u, 0xF0u, 0xFFu};
+
+template <uint32_t MASK>
+hipError_t launch_batch_mask(int slot, const BatchItem* d_items, int32_t n_items, int64_t n_tiles,
+                             uint32_t* d_counter, const int32_t* d_sched, hipStream_t stream) {
+  // blocks of this kernel the whole GPU keeps resident (per device and kernel, queried once)
+  static std::atomic<int> resident[3][64];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  int resident_blocks = (dev >= 0 && dev < 64) ? resident[dev].load(std::memory_order_relaxed) : 0;
+  int resident_blocks = (dev >= 0 && dev < 64) ? resident[slot][dev].load(std::memory_order_relaxed) : 0;
   if (resident_blocks == 0) {
     int cus = 0, per_cu = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_batch_kernel, kThreads, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_batch_kernel<MASK>, kThreads, 0);
     if (e != hipSuccess) return e;
     resident_blocks = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
-    if (dev >= 0 && dev < 64) resident[dev].store(resident_blocks, std::memory_order_relaxed);
+    if (dev >= 0 && dev < 64) resident[slot][dev].store(resident_blocks, std::memory_order_relaxed);
   }
   const int64_t want = (n_tiles + 3) / 4;  // 4 waves per block
   const unsigned blocks = (unsigned)(want < resident_blocks ? want : resident_blocks);
-  render_batch_kernel<<<blocks, kThreads, 0, stream>>>(d_items, n_items, n_tiles, d_counter, d_sched);
+  render_batch_kernel<MASK><<<blocks, kThreads, 0, stream>>>(d_items, n_items, n_tiles, d_counter, d_sched);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, uint32_t* d_counter,
+                               const int32_t* d_sched, uint32_t variants, hipStream_t stream) {
+  if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
+  if ((variants & ~kBatchMasks[0]) == 0)
+    return launch_batch_mask<kBatchMasks[0]>(0, d_items, n_items, n_tiles, d_counter, d_sched, stream);
+  if ((variants & ~kBatchMasks[1]) == 0)
+    return launch_batch_mask<kBatchMasks[1]>(1, d_items, n_items, n_tiles, d_counter, d_sched, stream);
+  return launch_batch_mask<kBatchMasks[2]>(2, d_items, n_items, n_tiles, d_counter, d_sched, stream);
 }
 
 hipError_t launch_backward(const BackwardParams& b, hipStream_t stream) {

@@ -160,6 +160,7 @@ bool salf_server::launch(Slot& s) {
   s.items.clear();
   s.tickets.clear();
   int64_t tiles = 0;
+  uint32_t variants = 0;
   while (!admitted.empty() && (int)s.items.size() < opts.max_batch) {
     Request& r = reqs[admitted.front()];
     if (!s.items.empty() && tiles + r.n_tiles > ((int64_t)1 << 30)) break;
@@ -168,6 +169,7 @@ bool salf_server::launch(Slot& s) {
     b.tile_begin = tiles;
     b.variant = r.variant;
     b.pad = 0;
+    variants |= 1u << (r.variant & 7);
     s.items.push_back(b);
     s.tickets.push_back(r.ticket);
     tiles += r.n_tiles;
@@ -181,7 +183,7 @@ bool salf_server::launch(Slot& s) {
   if (e == hipSuccess) e = launch_batch_schedule(s.d_items, (int32_t)s.items.size(), tiles, s.d_sched, s.stream);
   if (e == hipSuccess)
     e = launch_render_batch(s.d_items, (int32_t)s.items.size(), tiles, s.d_counter, (const int32_t*)s.d_sched,
-                            s.stream);
+                            variants, s.stream);
   if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
   if (e != hipSuccess) {
     const double t = now_s();
