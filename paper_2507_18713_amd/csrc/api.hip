@@ -126,13 +126,6 @@ salf_status salf::scene_snapshot(salf_context* ctx, int32_t id, Scene* out) {
 
 namespace {
 
-salf_status find_scene(salf_context* ctx, int32_t id, Scene** out) {
-  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
-  if (id < 0 || id >= (int32_t)ctx->scenes.size() || !ctx->scenes[id].live)
-    return set_error(SALF_ERR_NOT_FOUND, "no scene with id %d", id);
-  *out = &ctx->scenes[id];
-  return SALF_OK;
-}
 
 // The rays of a launch (sensor or explicit rays) and their tiling.
 salf_status ray_layout(const salf_sensor* sensor, const salf_rays* rays, RenderParams* p) {
@@ -180,13 +173,13 @@ salf_status check_work(const salf_render_opts* opts, const RenderParams& p) {
 // Fill the parts of RenderParams shared by render and backward.
 salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
                            const salf_render_opts* opts, RenderParams* p, int* field) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
   if (st) return st;
   if ((st = validate_opts(opts))) return st;
   memset(p, 0, sizeof(*p));
   if ((st = ray_layout(sensor, rays, p))) return st;
-  p->scene = sc->view;
+  p->scene = sc.view;
   if (opts->schedule != SALF_SCHEDULE_NONE) {
     if ((st = check_work(opts, *p))) return st;
     p->sched = (const int32_t*)opts->d_work;
@@ -194,7 +187,7 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
   p->S = opts->samples_per_voxel;
   p->t_min = opts->t_min;
   for (int c = 0; c < 3; ++c) p->bg[c] = opts->background[c];
-  *field = sc->desc.field;
+  *field = sc.desc.field;
   return SALF_OK;
 }
 
@@ -228,12 +221,25 @@ salf_status index_plan(salf_context* ctx, const Scene& sc, int32_t max_level, st
 
 size_t index_bytes(int64_t n_root, int64_t entries) { return ((size_t)n_root * 4 + 255) / 256 * 256 + (size_t)entries * 4; }
 
-salf_status check_index_args(salf_context* ctx, int32_t scene_id, int32_t max_level, Scene** sc) {
-  salf_status st = find_scene(ctx, scene_id, sc);
+salf_status check_index_args(salf_context* ctx, int32_t scene_id, int32_t max_level, Scene* sc) {
+  salf_status st = scene_snapshot(ctx, scene_id, sc);
   if (st) return st;
   if (max_level < 0 || max_level > SALF_MAX_INDEX_LEVEL)
     return set_error(SALF_ERR_INVALID_ARG, "index level %d outside [0, %d]", max_level, SALF_MAX_INDEX_LEVEL);
-  if ((*sc)->n >= ((int64_t)1 << 28)) return set_error(SALF_ERR_INVALID_ARG, "a dense leaf index holds < 2^28 voxels");
+  if (sc->n >= ((int64_t)1 << 28)) return set_error(SALF_ERR_INVALID_ARG, "a dense leaf index holds < 2^28 voxels");
+  return SALF_OK;
+}
+
+// Set a scene's index pointers, under the lock, if the scene is still the one `snap` was taken of
+// (it may have been destroyed, and its id reused, while the index was built).
+salf_status attach_index(salf_context* ctx, int32_t scene_id, const Scene& snap, const int32_t* boff,
+                         const uint32_t* entries) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].live ||
+      ctx->scenes[scene_id].view.root != snap.view.root)
+    return set_error(SALF_ERR_NOT_FOUND, "scene %d was destroyed while its index was built", scene_id);
+  ctx->scenes[scene_id].view.boff = boff;
+  ctx->scenes[scene_id].view.cidx = entries;
   return SALF_OK;
 }
 }  // namespace
@@ -369,58 +375,53 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
 }
 
 salf_status salf_scene_refresh(salf_context* ctx, int32_t scene_id, void* stream) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
   if (st) return st;
-  const SceneView& v = sc->view;
+  const SceneView& v = sc.view;
   if (v.act_geo == nullptr) return SALF_OK;
   DeviceGuard g(ctx->device);
-  return check_hip(launch_activate(v.geo, v.rgb, v.inten, sc->n, (float*)v.act_geo, (float*)v.act_rgb,
+  return check_hip(launch_activate(v.geo, v.rgb, v.inten, sc.n, (float*)v.act_geo, (float*)v.act_rgb,
                                    (float*)v.act_int, (hipStream_t)stream),
                    "activation launch");
 }
 
 salf_status salf_scene_get_stats(salf_context* ctx, int32_t scene_id, salf_scene_stats* out) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
   if (st) return st;
   if (!out) return set_error(SALF_ERR_INVALID_ARG, "out is NULL");
-  out->n_voxels = sc->n;
-  out->n_nodes = sc->counters.n_nodes;
-  out->n_root_cells = sc->layout.n_root;
-  out->n_occupied_roots = sc->counters.n_occupied;
-  out->workspace_bytes = sc->layout.total;
+  out->n_voxels = sc.n;
+  out->n_nodes = sc.counters.n_nodes;
+  out->n_root_cells = sc.layout.n_root;
+  out->n_occupied_roots = sc.counters.n_occupied;
+  out->workspace_bytes = sc.layout.total;
   return SALF_OK;
 }
 
 salf_status salf_scene_index_size(salf_context* ctx, int32_t scene_id, int32_t max_level, size_t* bytes) {
-  Scene* sc = nullptr;
+  Scene sc;
   salf_status st = check_index_args(ctx, scene_id, max_level, &sc);
   if (st) return st;
   if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
   std::vector<int32_t> boff;
   int64_t entries = 0;
-  if ((st = index_plan(ctx, *sc, max_level, &boff, &entries))) return st;
-  *bytes = index_bytes(sc->layout.n_root, entries);
+  if ((st = index_plan(ctx, sc, max_level, &boff, &entries))) return st;
+  *bytes = index_bytes(sc.layout.n_root, entries);
   return SALF_OK;
 }
 
 salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t max_level, void* d_index,
                                    size_t bytes, void* stream) {
-  Scene* sc = nullptr;
+  Scene sc;
   salf_status st = check_index_args(ctx, scene_id, max_level, &sc);
   if (st) return st;
-  if (max_level == 0) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    sc->view.boff = nullptr;
-    sc->view.cidx = nullptr;
-    return SALF_OK;
-  }
+  if (max_level == 0) return attach_index(ctx, scene_id, sc, nullptr, nullptr);
   if (!d_index || ((uintptr_t)d_index & 255u)) return set_error(SALF_ERR_INVALID_ARG, "index must be 256-byte aligned");
   std::vector<int32_t> boff;
   int64_t entries = 0;
-  if ((st = index_plan(ctx, *sc, max_level, &boff, &entries))) return st;
-  const int64_t n_root = sc->layout.n_root;
+  if ((st = index_plan(ctx, sc, max_level, &boff, &entries))) return st;
+  const int64_t n_root = sc.layout.n_root;
   const size_t need = index_bytes(n_root, entries);
   if (bytes < need) return set_error(SALF_ERR_OUT_OF_MEMORY, "index has %zu bytes, it needs %zu", bytes, need);
   DeviceGuard g(ctx->device);
@@ -430,20 +431,17 @@ salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t 
   uint32_t* d_entries = (uint32_t*)((char*)d_index + index_bytes(n_root, 0));
   if ((st = check_hip(hipMemcpyAsync(d_boff, boff.data(), n_root * 4, hipMemcpyHostToDevice, s), "copy index offsets")))
     return st;
-  if ((st = check_hip(launch_index_fill(sc->view, n_root, d_boff, d_entries, s), "index launch"))) return st;
+  if ((st = check_hip(launch_index_fill(sc.view, n_root, d_boff, d_entries, s), "index launch"))) return st;
   if ((st = check_hip(hipStreamSynchronize(s), "index build"))) return st;
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  sc->view.boff = d_boff;
-  sc->view.cidx = d_entries;
-  return SALF_OK;
+  return attach_index(ctx, scene_id, sc, d_boff, d_entries);
 }
 
 salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
-  if (st) return st;
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  sc->live = false;
+  if (scene_id < 0 || scene_id >= (int32_t)ctx->scenes.size() || !ctx->scenes[scene_id].live)
+    return set_error(SALF_ERR_NOT_FOUND, "no scene with id %d", scene_id);
+  ctx->scenes[scene_id].live = false;
   return SALF_OK;
 }
 
@@ -507,15 +505,15 @@ salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* ra
 
 salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
                             int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream) {
-  Scene* sc = nullptr;
-  salf_status st = find_scene(ctx, scene_id, &sc);
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
   if (st) return st;
   if ((st = validate_rays(rays))) return st;
   if (max_hits < 0) return set_error(SALF_ERR_INVALID_ARG, "max_hits must be >= 0");
   if (rays->n > 0 && (!d_counts || (max_hits > 0 && (!d_ids || !d_t_in || !d_t_out))))
     return set_error(SALF_ERR_INVALID_ARG, "output pointer is NULL");
   DeviceGuard g(ctx->device);
-  return check_hip(launch_trace(sc->view, *rays, max_hits, d_counts, d_ids, d_t_in, d_t_out, (hipStream_t)stream),
+  return check_hip(launch_trace(sc.view, *rays, max_hits, d_counts, d_ids, d_t_in, d_t_out, (hipStream_t)stream),
                    "trace launch");
 }
 

@@ -448,18 +448,14 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
-    // activated corner values (stored ones when the scene keeps them, else from the logits) and
-    // softplus' = sigmoid for density: with stored values sigmoid(z) = 1 - exp(-softplus(z))
-    float sp[8], dsp[8], cr[3][8], ci[8];
+    // activated corner values (stored ones when the scene keeps them, else from the logits)
+    float sp[8], cr[3][8], ci[8];
     {
       const float4* gp = reinterpret_cast<const float4*>((ACT ? s.act_geo : s.geo) + (int64_t)v * 8);
       const float4 g0 = gp[0], g1 = gp[1];
       const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        sp[i] = ACT ? g[i] : softplus_f(g[i]);
-        dsp[i] = ACT ? -expm1f(-g[i]) : sigmoid_f(g[i]);
-      }
+      for (int i = 0; i < 8; ++i) sp[i] = ACT ? g[i] : softplus_f(g[i]);
     }
     if (RGB) {
       const float4* cp = reinterpret_cast<const float4*>((ACT ? s.act_rgb : s.rgb) + (int64_t)v * 24);
@@ -480,13 +476,11 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     }
     float rel[3], stp[3], delta, sc;
     segment_frame(s, f, h, rS, rel, stp, delta, sc);
-    float ag[8], ar[3][8], ai[8];
+    // ag: dL/d(corner density) before the activation; aw: sum over samples of weight x corner
+    // weight, which times a channel's output gradient is that channel's corner gradient
+    float ag[8], aw[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ag[i] = 0.0f;
-      ai[i] = 0.0f;
-      ar[0][i] = ar[1][i] = ar[2][i] = 0.0f;
-    }
+    for (int i = 0; i < 8; ++i) ag[i] = aw[i] = 0.0f;
     for (int k = 0; k < S; ++k) {
       const float fk = (float)k + 0.5f;
       float u[3], w[8];
@@ -521,36 +515,27 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       }
       const float dsig = dtau * delta;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) ag[i] = fmaf(dsig, w[i], ag[i]);
-      if (RGB) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float gw = gC[ch] * wgt;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) ar[ch][i] = fmaf(gw, w[i], ar[ch][i]);
-        }
-      }
-      if (INT) {
-        const float gw = gI * wgt;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) ai[i] = fmaf(gw, w[i], ai[i]);
+      for (int i = 0; i < 8; ++i) {
+        ag[i] = fmaf(dsig, w[i], ag[i]);
+        aw[i] = fmaf(wgt, w[i], aw[i]);
       }
       T = Tn;
     }
     // this lane's gradient row for the voxel (activation derivative applied): 8 density corners,
-    // then 24 colour and 8 intensity corners when present
+    // then 24 colour and 8 intensity corners when present.  softplus' = sigmoid, and
+    // sigmoid(z) = 1 - exp(-softplus(z)), from the activated value either way.
 #pragma unroll
-    for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * dsp[i];
+    for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * -expm1f(-sp[i]);
     if (RGB) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          red[(8 + ch * 8 + i) * kRedStride + lane] = ar[ch][i] * cr[ch][i] * (1.0f - cr[ch][i]);
+          red[(8 + ch * 8 + i) * kRedStride + lane] = (gC[ch] * aw[i]) * (cr[ch][i] * (1.0f - cr[ch][i]));
     }
     if (INT) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) red[(kIntRow + i) * kRedStride + lane] = ai[i] * ci[i] * (1.0f - ci[i]);
+      for (int i = 0; i < 8; ++i) red[(kIntRow + i) * kRedStride + lane] = (gI * aw[i]) * (ci[i] * (1.0f - ci[i]));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
