@@ -1,4 +1,4 @@
-"""Analytic gradient of the composited outputs w.r.t. the raw corner logits (corner mode, float64).
+"""Analytic gradient of the composited outputs w.r.t. the raw field parameters (float64).
 
 Let the samples of a ray be j = 1..M in compositing order (the stop index M is held
 fixed), with tau_j = sigma_j delta_j, T_1 = 1, T_{j+1} = T_j exp(-tau_j), w_j = T_j - T_{j+1}
@@ -11,13 +11,19 @@ Differentiating:
     dtau_j/dsigma_j = delta_j
 and through the corner activations (softplus' = sigmoid, sigmoid' = s (1 - s)):
     dsigma_j/dz_geo[c] = W_c(x_j) sigmoid(z_geo[c]),   dc_j/dz_rgb[ch, c] = W_c(x_j) s (1 - s).
+In the paper's field (Eq. 1-2), sigma = exp(a . x + b) and c = sigmoid(A x + B SH(omega)), so with
+xh = (x, 1):
+    dsigma_j/dz_geo[0:4] = sigma_j xh_j,
+    dc_j[ch]/dz_rgb[ch, 0:3] = s (1 - s) x_j,   dc_j[ch]/dz_rgb[ch, 3:7] = s (1 - s) SH(omega),
+    di_j/dz_int[0:4] = i_j (1 - i_j) xh_j,
+and the remaining slots of each record are unused (zero gradient).
 The suffix sums are formed directly from their definition.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .field import corner_weights, sigmoid, softplus
+from .field import corner_weights, paper_field, sh_basis, sigmoid, softplus
 from .hitspec import PreparedScene, hit_list
 from .render import RenderOpts, _sample_points
 
@@ -31,13 +37,19 @@ def _ray_samples(ps: PreparedScene, o, d, opts: RenderOpts):
     rec = []
     for v, ti, to in zip(ids, t_ins, t_outs):
         for tk, x, dk in _sample_points(ps, o64, d64, v, float(ti), float(to), opts.samples):
-            W = corner_weights(x)
-            sigma = float(W @ softplus(sc.z_geo[v]))
-            rgb = sigmoid(sc.z_rgb[v]) @ W
-            inten = float(W @ sigmoid(sc.z_int[v])) if sc.z_int is not None else 0.0
+            if opts.field == "paper":
+                W = None
+                sigma, rgb, inten = paper_field(sc.z_geo[v], sc.z_rgb[v], sc.z_int[v] if sc.z_int is not None
+                                                else None, x, d64)
+            else:
+                W = corner_weights(x)
+                sigma = float(W @ softplus(sc.z_geo[v]))
+                rgb = sigmoid(sc.z_rgb[v]) @ W
+                inten = float(W @ sigmoid(sc.z_int[v])) if sc.z_int is not None else 0.0
             tau = sigma * dk
             Tn = T * np.exp(-tau)
-            rec.append(dict(v=v, W=W, rgb=rgb, inten=inten, tk=tk, dk=dk, T=T, Tn=Tn, w=T - Tn))
+            rec.append(dict(v=v, W=W, x=x, sigma=sigma, rgb=rgb, inten=inten, tk=tk, dk=dk, T=T, Tn=Tn,
+                            w=T - Tn, omega=d64))
             T = Tn
         if T < opts.t_min:
             break
@@ -47,8 +59,8 @@ def _ray_samples(ps: PreparedScene, o, d, opts: RenderOpts):
 def grad_rays(ps: PreparedScene, o, d, opts: RenderOpts, g_rgb, g_depth, g_opacity, g_int):
     """Gradient of L = sum_r (g_rgb[r] . C_r + g_depth[r] D_r + g_opacity[r] O_r + g_int[r] I_r)
     w.r.t. z_geo [N, 8], z_rgb [N, 3, 8] and z_int [N, 8] (float64)."""
-    if opts.field != "corner":
-        raise NotImplementedError("the analytic gradient covers the corner-interpolated field")
+    if opts.field not in ("corner", "paper"):
+        raise ValueError(f"unknown field {opts.field!r}")
     sc = ps.scene
     dg = np.zeros(sc.z_geo.shape)
     dr = np.zeros(sc.z_rgb.shape)
@@ -66,12 +78,21 @@ def grad_rays(ps: PreparedScene, o, d, opts: RenderOpts, g_rgb, g_depth, g_opaci
             dtau = (gC @ (s["Tn"] * s["rgb"] - sufC) + gD * (s["Tn"] * s["tk"] - sufD)
                     + gI * (s["Tn"] * s["inten"] - sufI) + gO * T_end)
             dsig = dtau * s["dk"]
-            dg[v] += dsig * s["W"] * sigmoid(sc.z_geo[v])
-            sr = sigmoid(sc.z_rgb[v])
-            dr[v] += (gC[:, None] * s["w"]) * s["W"][None, :] * sr * (1.0 - sr)
-            if sc.z_int is not None:
-                si = sigmoid(sc.z_int[v])
-                di[v] += gI * s["w"] * s["W"] * si * (1.0 - si)
+            if opts.field == "paper":
+                xh = np.append(s["x"], 1.0)
+                dg[v, :4] += dsig * s["sigma"] * xh
+                basis = np.concatenate([s["x"], sh_basis(s["omega"])])
+                c = s["rgb"]
+                dr[v, :, :7] += (gC * s["w"] * c * (1.0 - c))[:, None] * basis[None, :]
+                if sc.z_int is not None:
+                    di[v, :4] += gI * s["w"] * s["inten"] * (1.0 - s["inten"]) * xh
+            else:
+                dg[v] += dsig * s["W"] * sigmoid(sc.z_geo[v])
+                sr = sigmoid(sc.z_rgb[v])
+                dr[v] += (gC[:, None] * s["w"]) * s["W"][None, :] * sr * (1.0 - sr)
+                if sc.z_int is not None:
+                    si = sigmoid(sc.z_int[v])
+                    di[v] += gI * s["w"] * s["W"] * si * (1.0 - si)
             sufC = sufC + s["w"] * s["rgb"]
             sufD = sufD + s["w"] * s["tk"]
             sufI = sufI + s["w"] * s["inten"]

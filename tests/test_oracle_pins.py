@@ -509,6 +509,50 @@ def test_p11_oracle_gradient_matches_central_differences():
             assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
 
 
+def test_p11_oracle_paper_field_gradient_matches_central_differences():
+    """The same pin for the paper's field (Eq. 1-2): exponential-affine density, sigmoid colour
+    with a degree-1 SH term, sigmoid-affine intensity."""
+    sc = synth.random_scene(24, root_dims=(3, 3, 3), max_level=1, fill=0.7)
+    rng = np.random.default_rng(25)
+    n_v = sc.voxels.shape[0]
+    geo = np.zeros((n_v, 8))
+    geo[:, :3] = rng.normal(0, 0.5, (n_v, 3))
+    geo[:, 3] = rng.normal(0, 1, n_v)
+    rgb = np.zeros((n_v, 3, 8))
+    rgb[:, :, :7] = rng.normal(0, 0.7, (n_v, 3, 7))
+    ity = np.zeros((n_v, 8))
+    ity[:, :4] = rng.normal(0, 0.7, (n_v, 4))
+    sc64 = synth.SceneData(**{**sc.__dict__, "z_geo": geo, "z_rgb": rgb, "z_int": ity})
+    o, d = synth.random_rays(26, 24, sc.origin, sc.origin + sc.root_dims * sc.root_size, inside_frac=0.0)
+    n = o.shape[0]
+    g_rgb, g_d, g_o, g_i = rng.normal(size=(n, 3)), rng.normal(size=n), rng.normal(size=n), rng.normal(size=n)
+    opts = RenderOpts(samples=3, t_min=0.0, background=(0.1, 0.2, 0.3), field="paper")
+
+    def loss(s):
+        out = oracle.render_rays(oracle.prepare(s), o, d, opts)
+        return float(np.sum(g_rgb * out["rgb"]) + g_d @ out["depth"] + g_o @ out["opacity"] + g_i @ out["intensity"])
+
+    dg, dr, di = oracle.grad_rays(oracle.prepare(sc64), o, d, opts, g_rgb, g_d, g_o, g_i)
+    touched = np.nonzero(np.any(dg != 0, axis=1))[0]
+    assert touched.size > 5
+    # the unused slots of each record get no gradient
+    assert not dg[:, 4:].any() and not dr[:, :, 7].any() and not di[:, 4:].any()
+    eps = 1e-6
+    for name, arr, grad, width in (("z_geo", sc64.z_geo, dg, 4), ("z_rgb", sc64.z_rgb, dr, 7),
+                                   ("z_int", sc64.z_int, di, 4)):
+        for _ in range(8):
+            v = int(rng.choice(touched))
+            idx = (v,) + tuple(int(rng.integers(0, s)) for s in arr.shape[1:-1]) + (int(rng.integers(0, width)),)
+            old = arr[idx]
+            arr[idx] = old + eps
+            lp = loss(sc64)
+            arr[idx] = old - eps
+            lm = loss(sc64)
+            arr[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
+
+
 # ---------------------------------------------------------------- early termination
 def test_early_termination_after_the_voxel_that_crosses_t_min():
     # two voxels in a row along x; the first is nearly opaque (optical depth ~ 30 along x)
