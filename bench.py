@@ -313,6 +313,10 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
         fwd.append(e0.elapsed_time(em))
     loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
     ms = float(np.median(times))
+    grad_abs_sum = float(d_geo.abs().sum() + d_rgb.abs().sum())
+    g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
+    g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
+    paper = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps)
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
                         "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
                         "SGD update + activation refresh in the step",
@@ -320,7 +324,50 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),
             "mrays_s_fwd_bwd": round((n_cam + n_lid) / ms / 1e3, 2), "loss": round(loss, 5),
-            "grad_abs_sum": float(d_geo.abs().sum() + d_rgb.abs().sum())}
+            "grad_abs_sum": grad_abs_sum, "paper_field": paper}
+
+
+def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, seed=6):
+    """Forward and backward of the same batch on the driving scene's voxels with the paper's field
+    (Eq. 1-2): seeded parameters, density slopes N(0, 0.5^2) and offset N(0, 1) - 1, colour and
+    intensity slopes and SH coefficients N(0, 0.5^2), offsets N(0, 1).  Timed by HIP events; no
+    update."""
+    import numpy as np
+
+    import synth
+    rng = np.random.default_rng(seed)
+    n = data.n
+    geo = np.zeros((n, 8), np.float32)
+    geo[:, :3] = rng.normal(0, 0.5, (n, 3))
+    geo[:, 3] = rng.normal(0, 1, n) - 1.0
+    rgb = np.zeros((n, 3, 8), np.float32)
+    rgb[:, :, :3] = rng.normal(0, 0.5, (n, 3, 3))
+    rgb[:, :, 3] = rng.normal(0, 1, (n, 3))
+    rgb[:, :, 4:7] = rng.normal(0, 0.5, (n, 3, 3))
+    ity = np.zeros((n, 8), np.float32)
+    ity[:, :3] = rng.normal(0, 0.5, (n, 3))
+    ity[:, 3] = rng.normal(0, 1, n)
+    pdata = synth.SceneData(**{**data.__dict__, "z_geo": geo, "z_rgb": rgb, "z_int": ity})
+    scene = salf.Scene.from_data(pdata, device=dev, field="paper")
+    d_geo, d_rgb = torch.zeros_like(scene.geo), torch.zeros_like(scene.rgb)
+    outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
+    fwd, bwd = [], []
+    for i in range(steps + 2):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        fc = salf.render(scene, o=oc, d=dc, outputs=outs, **opts)
+        fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), **opts)
+        e1.record()
+        salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
+        salf.render_backward(scene, fl, {"depth": g_l}, o=ol, d=dl, d_geo=d_geo, **opts)
+        e2.record()
+        torch.cuda.synchronize()
+        if i >= 2:
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(e1.elapsed_time(e2))
+    scene.destroy()
+    return {"forward_ms_median": round(float(np.median(fwd)), 3), "backward_ms_median": round(float(np.median(bwd)), 3),
+            "shaded_hits_per_camera_ray": round(float(fc["n_hits"].double().mean()), 3)}
 
 
 # ------------------------------------------------------------------ HBM counter pass

@@ -323,8 +323,11 @@ typedef struct {
   const float* d_intensity; /* [n]    */
 } salf_grads_in;
 
-/* Gradient of a corner-field render w.r.t. the raw corner logits, accumulated (+=) into
- * d_dgeo [N, 8], d_drgb [N, 3, 8] and d_dint [N, 8] (NULL = not wanted; the caller zero-fills).
+/* Gradient of a render w.r.t. the scene's raw parameters, accumulated (+=) into d_dgeo [N, 8],
+ * d_drgb [N, 3, 8] and d_dint [N, 8] (NULL = not wanted; the caller zero-fills).  Corner field:
+ * w.r.t. the corner logits.  Paper field (Eq. 1-2): w.r.t. the density's slopes and offset
+ * (geo[0:4]), each colour channel's slopes and SH coefficients (rgb[ch][0:7]) and the
+ * intensity's slopes and offset (int[0:4]); the unused slots receive nothing.
  * `sensor`/`rays`, `opts` and the scene parameters must be those of the forward call, and
  * `saved` must hold its t_end and n_hits (rgb/depth/intensity as well when their gradient is
  * requested).  The kernel re-traverses each ray and recomputes transmittance front to back; no
@@ -332,8 +335,8 @@ typedef struct {
  * activated values in both passes (salf_scene_refresh after changing the logits), softplus'
  * being taken as 1 - exp(-softplus); the gradient is w.r.t. the logits either way.  Lanes of a
  * wave that hit the same voxel add their contributions first; the rest is accumulated with FP32
- * atomics, so the summation order (and the last bits) vary between runs.  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field),
- * DEVICE. */
+ * atomics, so the summation order (and the last bits) vary between runs.  Errors: INVALID_ARG,
+ * NOT_FOUND, DEVICE. */
 salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
                                  const salf_rays* rays, const salf_render_opts* opts,
                                  const salf_outputs* saved, const salf_grads_in* grads, float* d_dgeo,

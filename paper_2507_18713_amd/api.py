@@ -327,8 +327,8 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
                     sensor: Optional[dict] = None, o=None, d=None, samples: int = 4, t_min: float = 1e-6,
                     background=(0.0, 0.0, 0.0), t_near: float = 0.0, t_far: float = math.inf,
                     d_geo=None, d_rgb=None, d_int=None, image_width: int = 0, schedule=True):
-    """Accumulate dL/d(params) of a corner-field render into d_geo/d_rgb/d_int (allocated zeroed if
-    None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
+    """Accumulate dL/d(params) of a render (corner or paper field) into d_geo/d_rgb/d_int (allocated
+    zeroed if None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
     dev = scene.device
     if d_geo is None:
         d_geo = torch.zeros_like(scene.geo, memory_format=torch.contiguous_format)
@@ -361,7 +361,7 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
 
 
 class RenderFunction(torch.autograd.Function):
-    """Differentiable corner-field render.  apply(geo, rgb, intensity, scene, sensor, o, d, opts) ->
+    """Differentiable render (corner or paper field).  apply(geo, rgb, intensity, scene, sensor, o, d, opts) ->
     (rgb, depth, opacity, intensity); geo/rgb/intensity must be the scene's own parameter
     tensors (the render reads them in place).  rgb/intensity outputs are empty tensors when the
     scene lacks that parameter."""

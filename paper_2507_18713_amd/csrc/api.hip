@@ -524,8 +524,6 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
   int field = 0;
   salf_status st = prepare_render(ctx, scene_id, sensor, rays, opts, &b.fwd, &field);
   if (st) return st;
-  if (field != SALF_FIELD_CORNER)
-    return set_error(SALF_ERR_UNSUPPORTED, "the backward pass covers the corner-interpolated field");
   if (!saved || !grads) return set_error(SALF_ERR_INVALID_ARG, "saved outputs and gradients are required");
   if (!saved->t_end || !saved->n_hits) return set_error(SALF_ERR_INVALID_ARG, "saved t_end and n_hits are required");
   if (grads->d_rgb && (!saved->rgb || !b.fwd.scene.rgb))
@@ -544,7 +542,7 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
   if (opts->schedule == SALF_SCHEDULE_BUILD &&
       (st = check_hip(launch_tile_schedule(b.fwd, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
     return st;
-  return check_hip(launch_backward(b, (hipStream_t)stream), "backward launch");
+  return check_hip(launch_backward(b, field, (hipStream_t)stream), "backward launch");
 }
 
 }  // extern "C"

@@ -129,7 +129,8 @@ struct BackwardParams {
   float* drgb;
   float* dint;
 };
-hipError_t launch_backward(const BackwardParams& p, hipStream_t stream);
+// field: SALF_FIELD_CORNER or SALF_FIELD_PAPER (the scene's)
+hipError_t launch_backward(const BackwardParams& p, int field, hipStream_t stream);
 
 // A registered scene (the context's registry).
 struct Scene {

@@ -407,7 +407,8 @@ __global__ __launch_bounds__(kThreads) void raygen_kernel(salf_sensor s, float* 
 // dsigma_j = dL/dtau_j * delta_j, dc_j = gC w_j, di_j = gI w_j; corner logits get these times
 // the trilinear weight and the activation's derivative (softplus' = sigmoid, sigmoid' = s(1-s)).
 // Transmittance is recomputed front to back; the ray stops after the saved number of voxels.
-template <bool RGB, bool INT, bool ACT>
+// PAPER: the field of Eq. 1-2 (raw parameters; ACT is false), else the corner field.
+template <bool RGB, bool INT, bool ACT, bool PAPER>
 __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const RenderParams& p = b.fwd;
   int64_t ray;
@@ -445,18 +446,39 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   float* red = red_all + (threadIdx.x >> 6) * (kRows * kRedStride);
   const int lane = threadIdx.x & 63;
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  // degree-1 SH basis of the ray direction (paper field), as in the forward
+  const float shb[4] = {kShC0, kShC1 * dir[0], kShC1 * dir[1], kShC1 * dir[2]};
   traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
-    // activated corner values (stored ones when the scene keeps them, else from the logits)
+    // activated corner values (stored ones when the scene keeps them, else from the logits); for
+    // the paper field the raw parameters
     float sp[8], cr[3][8], ci[8];
-    {
+    if constexpr (PAPER) {
+      const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
+      const float4 g0 = gp[0];
+      sp[0] = g0.x; sp[1] = g0.y; sp[2] = g0.z; sp[3] = g0.w;
+      if (RGB) {
+        const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float4 a = cp[2 * ch], q = cp[2 * ch + 1];
+          cr[ch][0] = a.x; cr[ch][1] = a.y; cr[ch][2] = a.z; cr[ch][3] = a.w;
+          cr[ch][4] = q.x; cr[ch][5] = q.y; cr[ch][6] = q.z;
+          // the view-dependent term of the colour logit, as the forward forms it
+          cr[ch][7] = fmaf(cr[ch][3], shb[0], fmaf(cr[ch][4], shb[1], fmaf(cr[ch][5], shb[2], cr[ch][6] * shb[3])));
+        }
+      }
+      if (INT) {
+        const float4 a = reinterpret_cast<const float4*>(s.inten + (int64_t)v * 8)[0];
+        ci[0] = a.x; ci[1] = a.y; ci[2] = a.z; ci[3] = a.w;
+      }
+    } else {
       const float4* gp = reinterpret_cast<const float4*>((ACT ? s.act_geo : s.geo) + (int64_t)v * 8);
       const float4 g0 = gp[0], g1 = gp[1];
       const float g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
       for (int i = 0; i < 8; ++i) sp[i] = ACT ? g[i] : softplus_f(g[i]);
-    }
     if (RGB) {
       const float4* cp = reinterpret_cast<const float4*>((ACT ? s.act_rgb : s.rgb) + (int64_t)v * 24);
 #pragma unroll
@@ -474,6 +496,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) ci[i] = ACT ? z[i] : sigmoid_f(z[i]);
     }
+    }
     float rel[3], stp[3], delta, sc;
     segment_frame(s, f, h, rS, rel, stp, delta, sc);
     // ag: dL/d(corner density) before the activation; aw: sum over samples of weight x corner
@@ -481,20 +504,36 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     float ag[8], aw[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) ag[i] = aw[i] = 0.0f;
+    // paper field: per channel, the colour logit's gradient times (x, 1)
+    float pc[3][4];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) pc[ch][0] = pc[ch][1] = pc[ch][2] = pc[ch][3] = 0.0f;
     for (int k = 0; k < S; ++k) {
       const float fk = (float)k + 0.5f;
-      float u[3], w[8];
+      float u[3], w[8], x[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
-      corner_weights(u, w);
       // the forward's arithmetic, operation for operation, so T and the prefix sums match it
-      const float sigma = dot8(w, sp);
-      float col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-      if (RGB) {
+      float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
+      if constexpr (PAPER) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, cr[ch]);
+        for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
+        sigma = __expf(fmaf(sp[0], x[0], fmaf(sp[1], x[1], fmaf(sp[2], x[2], sp[3]))));
+        if (RGB) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch)
+            col[ch] = sigmoid_f(fmaf(cr[ch][0], x[0], fmaf(cr[ch][1], x[1], fmaf(cr[ch][2], x[2], cr[ch][7]))));
+        }
+        if (INT) inten = sigmoid_f(fmaf(ci[0], x[0], fmaf(ci[1], x[1], fmaf(ci[2], x[2], ci[3]))));
+      } else {
+        corner_weights(u, w);
+        sigma = dot8(w, sp);
+        if (RGB) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, cr[ch]);
+        }
+        if (INT) inten = dot8(w, ci);
       }
-      if (INT) inten = dot8(w, ci);
       const float e = __expf(-sigma * delta);
       const float wgt = T * (1.0f - e);
       const float Tn = T * e;
@@ -514,16 +553,58 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
         dtau = fmaf(gI, fmaf(Tn, inten, -(Is - PI)), dtau);
       }
       const float dsig = dtau * delta;
+      if constexpr (PAPER) {
+        // ag[0:4]: d/d(density parameters) = dsig sigma (x, 1); aw[ch * 2 + 0:1] hold no corner
+        // weights here: aw[0:3] and pc: d/d(colour logit) x (x, 1) per channel, pi likewise
+        const float ds = dsig * sigma;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        ag[i] = fmaf(dsig, w[i], ag[i]);
-        aw[i] = fmaf(wgt, w[i], aw[i]);
+        for (int a = 0; a < 3; ++a) ag[a] = fmaf(ds, x[a], ag[a]);
+        ag[3] += ds;
+        if (RGB) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float gl = gC[ch] * wgt * (col[ch] * (1.0f - col[ch]));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pc[ch][a] = fmaf(gl, x[a], pc[ch][a]);
+            pc[ch][3] += gl;
+          }
+        }
+        if (INT) {
+          const float gl = gI * wgt * (inten * (1.0f - inten));
+#pragma unroll
+          for (int a = 0; a < 3; ++a) aw[a] = fmaf(gl, x[a], aw[a]);
+          aw[3] += gl;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          ag[i] = fmaf(dsig, w[i], ag[i]);
+          aw[i] = fmaf(wgt, w[i], aw[i]);
+        }
       }
       T = Tn;
     }
     // this lane's gradient row for the voxel (activation derivative applied): 8 density corners,
     // then 24 colour and 8 intensity corners when present.  softplus' = sigmoid, and
-    // sigmoid(z) = 1 - exp(-softplus(z)), from the activated value either way.
+    // sigmoid(z) = 1 - exp(-softplus(z)), from the activated value either way.  The paper
+    // field's rows follow its record layout (density a, b; per channel A, then the SH
+    // coefficients B times the basis; intensity a, b), zero in the unused slots.
+    if constexpr (PAPER) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = i < 4 ? ag[i] : 0.0f;
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            red[(8 + ch * 8 + i) * kRedStride + lane] =
+                i < 3 ? pc[ch][i] : (i < 7 ? pc[ch][3] * shb[i - 3] : 0.0f);
+      }
+      if (INT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[(kIntRow + i) * kRedStride + lane] = i < 4 ? aw[i] : 0.0f;
+      }
+    } else {
 #pragma unroll
     for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = ag[i] * -expm1f(-sp[i]);
     if (RGB) {
@@ -536,6 +617,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     if (INT) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) red[(kIntRow + i) * kRedStride + lane] = (gI * aw[i]) * (ci[i] * (1.0f - ci[i]));
+    }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -554,6 +636,8 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     const int size = __popcll(mine);
     const int rank = __popcll(mine & ((1ull << lane) - 1ull));
     for (int j = rank; j < kRows; j += size) {
+      // the paper field's unused record slots get no atomics
+      if (PAPER && (j < 8 ? j >= 4 : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) continue;
       float sum = 0.0f;
       for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
       float* dst = j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
@@ -687,22 +771,27 @@ hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_
   return launch_batch_mask<kBatchMasks[2]>(2, d_items, n_items, n_tiles, d_counter, d_sched, stream);
 }
 
-hipError_t launch_backward(const BackwardParams& b, hipStream_t stream) {
+hipError_t launch_backward(const BackwardParams& b, int field, hipStream_t stream) {
   const RenderParams& p = b.fwd;
   const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
   const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
-  if (p.scene.act_geo != nullptr) {
-    if (rgb && in) backward_kernel<true, true, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, true><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, true><<<blocks, kThreads, 0, stream>>>(b);
+  if (field == SALF_FIELD_PAPER) {
+    if (rgb && in) backward_kernel<true, true, false, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, true><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, true><<<blocks, kThreads, 0, stream>>>(b);
+  } else if (p.scene.act_geo != nullptr) {
+    if (rgb && in) backward_kernel<true, true, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
   } else {
-    if (rgb && in) backward_kernel<true, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    if (rgb && in) backward_kernel<true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
   }
   return hipGetLastError();
 }

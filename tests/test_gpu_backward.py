@@ -1,5 +1,6 @@
-"""GPU backward pass (corner field): against the oracle's analytic gradient on small scenes, and
-against central finite differences of the GPU forward on the driving scene.
+"""GPU backward pass: against the oracle's analytic gradient on small scenes (corner field and the
+paper's field of Eq. 1-2), and against central finite differences of the GPU forward on the
+driving scene (corner field) and on a small paper-field scene.
 
 Bars: GPU vs oracle |g - g_o| <= 1e-3 |g_o| + 1e-5 max|g_o|; GPU vs FD (eps = 1e-3, loss summed in
 float64, t_min = 0) |g - g_fd| <= 2e-2 |g_fd| + 1e-3 max|g_fd|.
@@ -58,6 +59,98 @@ def test_gradient_matches_oracle(salf, which):
     _close(dg.cpu().numpy(), eg)
     _close(dr.cpu().numpy(), er)
     _close(di.cpu().numpy(), ei)
+
+
+def _paper_scene(seed):
+    """A seeded scene with Eq. 1-2 parameters: density slopes N(0, 0.5^2) and offset N(0, 1); colour
+    slopes and SH coefficients N(0, 0.5^2), offsets N(0, 1); intensity likewise (as the paper-field
+    forward test)."""
+    data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=2)
+    rng = np.random.default_rng(seed + 1)
+    n = data.n
+    geo = np.zeros((n, 8), np.float32)
+    geo[:, :3] = rng.normal(0, 0.5, (n, 3))
+    geo[:, 3] = rng.normal(0, 1, n)
+    rgb = np.zeros((n, 3, 8), np.float32)
+    rgb[:, :, :3] = rng.normal(0, 0.5, (n, 3, 3))
+    rgb[:, :, 3] = rng.normal(0, 1, (n, 3))
+    rgb[:, :, 4:7] = rng.normal(0, 0.5, (n, 3, 3))
+    ity = np.zeros((n, 8), np.float32)
+    ity[:, :3] = rng.normal(0, 0.5, (n, 3))
+    ity[:, 3] = rng.normal(0, 1, n)
+    data.z_geo, data.z_rgb, data.z_int = geo, rgb, ity
+    return data
+
+
+@pytest.mark.parametrize("samples", [1, 4])
+def test_paper_field_gradient_matches_oracle(salf, samples):
+    data = _paper_scene(85)
+    o, d = synth.random_rays(87, 600, data.origin, data.origin + data.root_dims * data.root_size)
+    n = o.shape[0]
+    rng = np.random.default_rng(88)
+    g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+    g_d, g_o, g_i = (rng.normal(size=n).astype(np.float32) for _ in range(3))
+    bg = (0.1, 0.2, 0.3)
+    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    saved = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg, samples=samples, outputs=outs)
+    grads = {"rgb": to_dev(g_rgb), "depth": to_dev(g_d), "opacity": to_dev(g_o), "intensity": to_dev(g_i)}
+    dg, dr, di = salf.render_backward(scene, saved, grads, o=to_dev(o), d=to_dev(d), background=bg,
+                                      samples=samples)
+    eg, er, ei = oracle.grad_rays(oracle.prepare(data), o, d, RenderOpts(background=bg, samples=samples,
+                                                                          field="paper"),
+                                  g_rgb, g_d, g_o, g_i)
+    dg, dr, di = dg.cpu().numpy(), dr.cpu().numpy(), di.cpu().numpy()
+    # the unused record slots receive nothing
+    assert not dg[:, 4:].any() and not dr[:, :, 7].any() and not di[:, 4:].any()
+    _close(dg, eg)
+    _close(dr, er)
+    _close(di, ei)
+
+
+def test_paper_field_gradient_matches_finite_differences(salf):
+    """Central differences (eps = 1e-3) of the GPU forward, summed in float64, on a paper-field
+    scene: the parameters are drawn from voxels that at least 8 of the rays hit."""
+    data = _paper_scene(89)
+    lo, hi = data.origin, data.origin + data.root_dims * data.root_size
+    o, d = synth.random_rays(90, 4000, lo, hi)
+    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    opts = dict(samples=4, t_min=0.0)
+    O, D = to_dev(o), to_dev(d)
+    n = o.shape[0]
+    rng = np.random.default_rng(92)
+    g_rgb = torch.from_numpy(rng.normal(size=(n, 3)).astype(np.float32)).to(dev())
+    g_d = torch.from_numpy(rng.normal(size=n).astype(np.float32)).to(dev())
+
+    def loss():
+        r = salf.render(scene, o=O, d=D, outputs=("rgb", "depth"), **opts)
+        return float((g_rgb.double() * r["rgb"].double()).sum() + (g_d.double() * r["depth"].double()).sum())
+
+    saved = salf.render(scene, o=O, d=D, outputs=("rgb", "depth", "opacity", "t_end", "n_hits"), **opts)
+    dg, dr, _ = salf.render_backward(scene, saved, {"rgb": g_rgb, "depth": g_d}, o=O, d=D, **opts)
+    cnt, ids, _, _ = salf.trace_hits(scene, O, D, 256)
+    ids = ids.cpu().numpy()
+    hits = np.bincount(ids[ids >= 0], minlength=data.n)
+    cand = np.nonzero(hits >= 8)[0]
+    assert cand.size >= 10
+    eps = 1e-3
+    checks = []
+    for arr, grad, width in ((scene.geo, dg, 4), (scene.rgb, dr, 7)):
+        for _ in range(12):
+            v = int(rng.choice(cand))
+            idx = (v,) + ((int(rng.integers(0, 3)),) if arr.dim() == 3 else ()) + (int(rng.integers(0, width)),)
+            old = float(arr[idx])
+            arr[idx] = old + eps
+            lp = loss()
+            arr[idx] = old - eps
+            lm = loss()
+            arr[idx] = old
+            checks.append(((lp - lm) / (2 * eps), float(grad[idx])))
+    fd = np.array([c[0] for c in checks])
+    g = np.array([c[1] for c in checks])
+    scale = np.max(np.abs(fd))
+    assert scale > 0
+    assert np.all(np.abs(g - fd) <= 2e-2 * np.abs(fd) + 1e-3 * scale), list(zip(fd, g))
 
 
 def test_gradient_matches_finite_differences_on_driving_scene(salf):
