@@ -14,6 +14,13 @@ paper mode    Eq. 1: sigma = exp(W_sigma [x, 1]) with W_sigma = z_geo[v, 0:4].
               gamma(omega) = (C0, C1 wx, C1 wy, C1 wz) is the real spherical-harmonic basis of
               degree <= 1 (4 coefficients) at the view direction omega.
               Intensity (a LiDAR channel the paper does not define): sigmoid(z_int[v, 0:4] [x, 1]).
+
+sdf mode      Surface parameterization (Eq. 5-6): the density of paper mode is replaced by a
+              signed distance s = W_s [x, 1] with W_s = z_geo[v, 0:4], turned into density by
+              sigma = a/2 + a/2 sign(s) (1 - exp(-|s| / b)); the voxel's a, b are stored as
+              logarithms, a = exp(z_geo[v, 4]), b = exp(z_geo[v, 5]), so that they stay positive
+              under any update (the paper does not say how they are kept positive).  Colour and
+              intensity as in paper mode.
 """
 from __future__ import annotations
 
@@ -60,6 +67,23 @@ def corner_field(z_geo_v, z_rgb_v, z_int_v, x):
 def sh_basis(omega):
     omega = np.asarray(omega, np.float64)
     return np.array([SH_C0, SH_C1 * omega[0], SH_C1 * omega[1], SH_C1 * omega[2]])
+
+
+def sdf_density(z_geo_v, x):
+    """(sigma, s, a, b) of Eq. 5-6 at local coordinates x."""
+    xh = np.append(np.asarray(x, np.float64), 1.0)
+    z = np.asarray(z_geo_v, np.float64)
+    s = float(z[:4] @ xh)
+    a, b = math.exp(z[4]), math.exp(z[5])
+    sigma = a / 2.0 + a / 2.0 * np.sign(s) * (1.0 - math.exp(-abs(s) / b))
+    return float(sigma), s, a, b
+
+
+def sdf_field(z_geo_v, z_rgb_v, z_int_v, x, omega):
+    """(sigma, rgb [3], intensity) of one voxel in sdf mode (Eq. 5-6 density, Eq. 2 colour)."""
+    sigma = sdf_density(z_geo_v, x)[0]
+    _, rgb, inten = paper_field(z_geo_v, z_rgb_v, z_int_v, x, omega)
+    return sigma, rgb, inten
 
 
 def paper_field(z_geo_v, z_rgb_v, z_int_v, x, omega):

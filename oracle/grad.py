@@ -16,14 +16,19 @@ xh = (x, 1):
     dsigma_j/dz_geo[0:4] = sigma_j xh_j,
     dc_j[ch]/dz_rgb[ch, 0:3] = s (1 - s) x_j,   dc_j[ch]/dz_rgb[ch, 3:7] = s (1 - s) SH(omega),
     di_j/dz_int[0:4] = i_j (1 - i_j) xh_j,
-and the remaining slots of each record are unused (zero gradient).
+and the remaining slots of each record are unused (zero gradient).  In the SDF variant (Eq. 5-6)
+the density is sigma = a/2 + a/2 sign(s) (1 - exp(-|s|/b)) with s = z_geo[0:4] . xh,
+a = exp(z_geo[4]), b = exp(z_geo[5]); with e = exp(-|s|/b):
+    dsigma/dz_geo[0:4] = (a / (2 b)) e xh,   dsigma/dz_geo[4] = sigma,
+    dsigma/dz_geo[5] = -(a / 2) (s / b) e,
+and colour and intensity as in the paper's field.
 The suffix sums are formed directly from their definition.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .field import corner_weights, paper_field, sh_basis, sigmoid, softplus
+from .field import corner_weights, paper_field, sdf_density, sh_basis, sigmoid, softplus
 from .hitspec import PreparedScene, hit_list
 from .render import RenderOpts, _sample_points
 
@@ -37,10 +42,12 @@ def _ray_samples(ps: PreparedScene, o, d, opts: RenderOpts):
     rec = []
     for v, ti, to in zip(ids, t_ins, t_outs):
         for tk, x, dk in _sample_points(ps, o64, d64, v, float(ti), float(to), opts.samples):
-            if opts.field == "paper":
+            if opts.field in ("paper", "sdf"):
                 W = None
                 sigma, rgb, inten = paper_field(sc.z_geo[v], sc.z_rgb[v], sc.z_int[v] if sc.z_int is not None
                                                 else None, x, d64)
+                if opts.field == "sdf":
+                    sigma, s_sd, a_sd, b_sd = sdf_density(sc.z_geo[v], x)
             else:
                 W = corner_weights(x)
                 sigma = float(W @ softplus(sc.z_geo[v]))
@@ -48,8 +55,11 @@ def _ray_samples(ps: PreparedScene, o, d, opts: RenderOpts):
                 inten = float(W @ sigmoid(sc.z_int[v])) if sc.z_int is not None else 0.0
             tau = sigma * dk
             Tn = T * np.exp(-tau)
-            rec.append(dict(v=v, W=W, x=x, sigma=sigma, rgb=rgb, inten=inten, tk=tk, dk=dk, T=T, Tn=Tn,
-                            w=T - Tn, omega=d64))
+            r = dict(v=v, W=W, x=x, sigma=sigma, rgb=rgb, inten=inten, tk=tk, dk=dk, T=T, Tn=Tn,
+                     w=T - Tn, omega=d64)
+            if opts.field == "sdf":
+                r.update(s=s_sd, a=a_sd, b=b_sd)
+            rec.append(r)
             T = Tn
         if T < opts.t_min:
             break
@@ -59,7 +69,7 @@ def _ray_samples(ps: PreparedScene, o, d, opts: RenderOpts):
 def grad_rays(ps: PreparedScene, o, d, opts: RenderOpts, g_rgb, g_depth, g_opacity, g_int):
     """Gradient of L = sum_r (g_rgb[r] . C_r + g_depth[r] D_r + g_opacity[r] O_r + g_int[r] I_r)
     w.r.t. z_geo [N, 8], z_rgb [N, 3, 8] and z_int [N, 8] (float64)."""
-    if opts.field not in ("corner", "paper"):
+    if opts.field not in ("corner", "paper", "sdf"):
         raise ValueError(f"unknown field {opts.field!r}")
     sc = ps.scene
     dg = np.zeros(sc.z_geo.shape)
@@ -78,9 +88,15 @@ def grad_rays(ps: PreparedScene, o, d, opts: RenderOpts, g_rgb, g_depth, g_opaci
             dtau = (gC @ (s["Tn"] * s["rgb"] - sufC) + gD * (s["Tn"] * s["tk"] - sufD)
                     + gI * (s["Tn"] * s["inten"] - sufI) + gO * T_end)
             dsig = dtau * s["dk"]
-            if opts.field == "paper":
+            if opts.field in ("paper", "sdf"):
                 xh = np.append(s["x"], 1.0)
-                dg[v, :4] += dsig * s["sigma"] * xh
+                if opts.field == "sdf":
+                    e = np.exp(-abs(s["s"]) / s["b"])
+                    dg[v, :4] += dsig * (s["a"] / (2.0 * s["b"])) * e * xh
+                    dg[v, 4] += dsig * s["sigma"]
+                    dg[v, 5] += dsig * (-(s["a"] / 2.0) * (s["s"] / s["b"]) * e)
+                else:
+                    dg[v, :4] += dsig * s["sigma"] * xh
                 basis = np.concatenate([s["x"], sh_basis(s["omega"])])
                 c = s["rgb"]
                 dr[v, :, :7] += (gC * s["w"] * c * (1.0 - c))[:, None] * basis[None, :]

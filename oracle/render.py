@@ -20,7 +20,7 @@ from typing import Sequence
 
 import numpy as np
 
-from .field import corner_field, paper_field
+from .field import corner_field, paper_field, sdf_field
 from .hitspec import PreparedScene, hit_list
 
 
@@ -31,7 +31,7 @@ class RenderOpts:
     background: Sequence[float] = (0.0, 0.0, 0.0)
     t_near: float = 0.0
     t_far: float = float("inf")
-    field: str = "corner"            # "corner" | "paper"
+    field: str = "corner"            # "corner" | "paper" | "sdf"
 
 
 def _sample_points(ps: PreparedScene, o64, d64, v, t_in, t_out, S):
@@ -65,6 +65,8 @@ def render_ray(ps: PreparedScene, o, d, opts: RenderOpts, hits=None):
         for tk, x, dk in _sample_points(ps, o64, d64, v, float(ti), float(to), opts.samples):
             if opts.field == "corner":
                 sigma, rgb, inten = corner_field(zg, zr, zi, x)
+            elif opts.field == "sdf":
+                sigma, rgb, inten = sdf_field(zg, zr, zi, x, d64)
             else:
                 sigma, rgb, inten = paper_field(zg, zr, zi, x, d64)
             tau = sigma * dk

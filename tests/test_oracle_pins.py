@@ -553,6 +553,80 @@ def test_p11_oracle_paper_field_gradient_matches_central_differences():
             assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
 
 
+def _sdf_scene(seed):
+    sc = synth.random_scene(seed, root_dims=(3, 3, 3), max_level=1, fill=0.7)
+    rng = np.random.default_rng(seed + 1)
+    n_v = sc.voxels.shape[0]
+    geo = np.zeros((n_v, 8))
+    geo[:, :3] = rng.normal(0, 0.6, (n_v, 3))
+    geo[:, 3] = rng.normal(0, 0.5, n_v)
+    geo[:, 4] = rng.normal(0.5, 0.3, n_v)      # log a
+    geo[:, 5] = rng.normal(-1.0, 0.3, n_v)     # log b
+    rgb = np.zeros((n_v, 3, 8))
+    rgb[:, :, :7] = rng.normal(0, 0.7, (n_v, 3, 7))
+    ity = np.zeros((n_v, 8))
+    ity[:, :4] = rng.normal(0, 0.7, (n_v, 4))
+    return synth.SceneData(**{**sc.__dict__, "z_geo": geo, "z_rgb": rgb, "z_int": ity})
+
+
+def test_sdf_density_is_a_scaled_laplace_cdf():
+    """Eq. 6 is a times the CDF of a Laplace distribution of scale b at s (the VolSDF form):
+    a/2 at s = 0, sigma(s) + sigma(-s) = a, a at s -> +inf, 0 at s -> -inf."""
+    from scipy.stats import laplace
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        z = np.zeros(8)
+        z[:4] = rng.normal(0, 2.0, 4)
+        z[4], z[5] = rng.normal(0, 1), rng.normal(-1, 1)
+        x = rng.uniform(-1, 1, 3)
+        sigma, s, a, b = oracle.sdf_density(z, x)
+        assert abs(s - (z[:3] @ x + z[3])) < 1e-12
+        assert abs(sigma - a * laplace.cdf(s, scale=b)) <= 1e-12 * a
+        zm = z.copy()
+        zm[:4] = -zm[:4]
+        assert abs(sigma + oracle.sdf_density(zm, x)[0] - a) <= 1e-12 * a
+    z = np.array([0.0, 0.0, 0.0, 0.0, math.log(3.0), math.log(0.1), 0.0, 0.0])
+    assert abs(oracle.sdf_density(z, np.zeros(3))[0] - 1.5) < 1e-12
+    z[3] = 50.0
+    assert abs(oracle.sdf_density(z, np.zeros(3))[0] - 3.0) < 1e-12
+    z[3] = -50.0
+    assert oracle.sdf_density(z, np.zeros(3))[0] < 1e-12
+
+
+def test_p11_oracle_sdf_gradient_matches_central_differences():
+    """The central-difference pin for the SDF variant (Eq. 5-6), including a and b."""
+    sc64 = _sdf_scene(27)
+    rng = np.random.default_rng(29)
+    o, d = synth.random_rays(28, 24, sc64.origin, sc64.origin + sc64.root_dims * sc64.root_size, inside_frac=0.0)
+    n = o.shape[0]
+    g_rgb, g_d, g_o, g_i = rng.normal(size=(n, 3)), rng.normal(size=n), rng.normal(size=n), rng.normal(size=n)
+    opts = RenderOpts(samples=3, t_min=0.0, background=(0.1, 0.2, 0.3), field="sdf")
+
+    def loss(s):
+        out = oracle.render_rays(oracle.prepare(s), o, d, opts)
+        return float(np.sum(g_rgb * out["rgb"]) + g_d @ out["depth"] + g_o @ out["opacity"] + g_i @ out["intensity"])
+
+    dg, dr, di = oracle.grad_rays(oracle.prepare(sc64), o, d, opts, g_rgb, g_d, g_o, g_i)
+    touched = np.nonzero(np.any(dg != 0, axis=1))[0]
+    assert touched.size > 5
+    assert not dg[:, 6:].any() and not dr[:, :, 7].any() and not di[:, 4:].any()
+    eps = 1e-6
+    for name, arr, grad, width in (("z_geo", sc64.z_geo, dg, 6), ("z_rgb", sc64.z_rgb, dr, 7),
+                                   ("z_int", sc64.z_int, di, 4)):
+        for k in range(10):
+            v = int(rng.choice(touched))
+            last = (k % width) if name == "z_geo" else int(rng.integers(0, width))
+            idx = (v,) + tuple(int(rng.integers(0, s)) for s in arr.shape[1:-1]) + (last,)
+            old = arr[idx]
+            arr[idx] = old + eps
+            lp = loss(sc64)
+            arr[idx] = old - eps
+            lm = loss(sc64)
+            arr[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
+
+
 # ---------------------------------------------------------------- early termination
 def test_early_termination_after_the_voxel_that_crosses_t_min():
     # two voxels in a row along x; the first is nearly opaque (optical depth ~ 30 along x)
