@@ -317,6 +317,7 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
     g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
     paper = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps)
+    sdf = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, field="sdf")
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
                         "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
                         "SGD update + activation refresh in the step",
@@ -324,14 +325,15 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),
             "mrays_s_fwd_bwd": round((n_cam + n_lid) / ms / 1e3, 2), "loss": round(loss, 5),
-            "grad_abs_sum": grad_abs_sum, "paper_field": paper}
+            "grad_abs_sum": grad_abs_sum, "paper_field": paper, "sdf_field": sdf}
 
 
-def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, seed=6):
+def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, seed=6, field="paper"):
     """Forward and backward of the same batch on the driving scene's voxels with the paper's field
     (Eq. 1-2): seeded parameters, density slopes N(0, 0.5^2) and offset N(0, 1) - 1, colour and
-    intensity slopes and SH coefficients N(0, 0.5^2), offsets N(0, 1).  Timed by HIP events; no
-    update."""
+    intensity slopes and SH coefficients N(0, 0.5^2), offsets N(0, 1).  field="sdf": the density
+    of Eq. 5-6 instead, signed-distance slopes N(0, 0.6^2) and offset N(0, 0.5^2), log a ~
+    N(0.5, 0.3^2), log b ~ N(-1, 0.3^2).  Timed by HIP events; no update."""
     import numpy as np
 
     import synth
@@ -340,6 +342,11 @@ def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, ste
     geo = np.zeros((n, 8), np.float32)
     geo[:, :3] = rng.normal(0, 0.5, (n, 3))
     geo[:, 3] = rng.normal(0, 1, n) - 1.0
+    if field == "sdf":
+        geo[:, :3] = rng.normal(0, 0.6, (n, 3))
+        geo[:, 3] = rng.normal(0, 0.5, n)
+        geo[:, 4] = rng.normal(0.5, 0.3, n)
+        geo[:, 5] = rng.normal(-1.0, 0.3, n)
     rgb = np.zeros((n, 3, 8), np.float32)
     rgb[:, :, :3] = rng.normal(0, 0.5, (n, 3, 3))
     rgb[:, :, 3] = rng.normal(0, 1, (n, 3))
@@ -348,7 +355,7 @@ def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, ste
     ity[:, :3] = rng.normal(0, 0.5, (n, 3))
     ity[:, 3] = rng.normal(0, 1, n)
     pdata = synth.SceneData(**{**data.__dict__, "z_geo": geo, "z_rgb": rgb, "z_int": ity})
-    scene = salf.Scene.from_data(pdata, device=dev, field="paper")
+    scene = salf.Scene.from_data(pdata, device=dev, field=field)
     d_geo, d_rgb = torch.zeros_like(scene.geo), torch.zeros_like(scene.rgb)
     outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
     fwd, bwd = [], []

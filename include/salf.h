@@ -60,6 +60,10 @@
  *     basis gamma(omega) = (C0, C1 wx, C1 wy, C1 wz), C0 = 1/(2 sqrt(pi)), C1 = sqrt(3)/(2 sqrt(pi)),
  *     omega = the ray direction; intensity = sigmoid(intensity[0:4] . [x, 1]).  Unused entries of
  *     each 8-float row are ignored.
+ *   SALF_FIELD_SDF (Eq. 5-6 with Eq. 2): signed distance s = geo[0:4] . [x, 1] and density
+ *     sigma = a/2 + a/2 sign(s) (1 - exp(-|s| / b)) with a = exp(geo[4]), b = exp(geo[5]) (the
+ *     voxel's SDF-to-density parameters, kept positive through their logarithms); colour and
+ *     intensity as SALF_FIELD_PAPER.
  */
 #ifndef SALF_H
 #define SALF_H
@@ -85,7 +89,7 @@ enum {
   SALF_ERR_UNSUPPORTED = -7    /* a valid but unimplemented combination                             */
 };
 
-enum { SALF_FIELD_CORNER = 0, SALF_FIELD_PAPER = 1 };
+enum { SALF_FIELD_CORNER = 0, SALF_FIELD_PAPER = 1, SALF_FIELD_SDF = 2 };
 enum { SALF_PINHOLE = 0, SALF_FISHEYE_EQUIDISTANT = 1, SALF_LIDAR_SPINNING = 2 };
 
 #define SALF_MAX_LEVEL 8         /* K <= 8                                                         */
@@ -121,7 +125,7 @@ typedef struct {
   double root_size;      /* s0, edge of a root cell (m), > 0                                         */
   int32_t root_dims[3];  /* root cells per axis, >= 1                                                */
   int32_t max_level;     /* K in [0, SALF_MAX_LEVEL]                                                 */
-  int32_t field;         /* SALF_FIELD_CORNER or SALF_FIELD_PAPER                                    */
+  int32_t field;         /* SALF_FIELD_CORNER, SALF_FIELD_PAPER or SALF_FIELD_SDF                    */
   int32_t flags;         /* 0 or SALF_SCENE_PREACTIVATE                                              */
 } salf_scene_desc;
 

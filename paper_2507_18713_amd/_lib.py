@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libsalf.so")
 SALF_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUDGET",
                 -6: "BUSY", -7: "UNSUPPORTED"}
-FIELD_CORNER, FIELD_PAPER = 0, 1
+FIELD_CORNER, FIELD_PAPER, FIELD_SDF = 0, 1, 2
 SCENE_PREACTIVATE = 1
 SCHEDULE_NONE, SCHEDULE_BUILD, SCHEDULE_REUSE = 0, 1, 2
 MAX_INDEX_LEVEL = 6  # SALF_MAX_INDEX_LEVEL

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import call
 
 OUTPUT_NAMES = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
-FIELDS = {"corner": _lib.FIELD_CORNER, "paper": _lib.FIELD_PAPER}
+FIELDS = {"corner": _lib.FIELD_CORNER, "paper": _lib.FIELD_PAPER, "sdf": _lib.FIELD_SDF}
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -62,7 +62,7 @@ salf_status validate_desc(const salf_scene_desc* d) {
     if (((int64_t)d->root_dims[a] << d->max_level) >= SALF_MAX_FINE_CELLS)
       return set_error(SALF_ERR_INVALID_ARG, "root_dims[%d] << max_level must be < %d", a, SALF_MAX_FINE_CELLS);
   }
-  if (d->field != SALF_FIELD_CORNER && d->field != SALF_FIELD_PAPER)
+  if (d->field != SALF_FIELD_CORNER && d->field != SALF_FIELD_PAPER && d->field != SALF_FIELD_SDF)
     return set_error(SALF_ERR_INVALID_ARG, "unknown field mode %d", d->field);
   if (d->flags & ~SALF_SCENE_PREACTIVATE) return set_error(SALF_ERR_INVALID_ARG, "unknown scene flags %d", d->flags);
   if ((d->flags & SALF_SCENE_PREACTIVATE) && d->field != SALF_FIELD_CORNER)

@@ -19,6 +19,8 @@ constexpr int32_t kEmpty = -1;          // empty cell / child
 // Field variants of the render kernels: the two of salf.h plus the corner field read from stored
 // activated corner values.
 constexpr int kFieldCornerActivated = 2;
+// The SDF variant's render kernels (SALF_FIELD_SDF scenes).
+constexpr int kFieldSdf = 3;
 __host__ __device__ inline bool is_leaf_code(int32_t c) { return c <= -2; }
 __host__ __device__ inline int32_t leaf_code(int32_t voxel) { return -2 - voxel; }
 __host__ __device__ inline int32_t leaf_voxel(int32_t code) { return -2 - code; }

@@ -24,6 +24,13 @@ struct Accum {
 
 // Shade one voxel segment [ti, to] and composite it into acc.  Returns false once the ray has
 // become opaque enough to stop (T < t_min after the voxel).
+// Density of the SDF variant (Eq. 6) at signed distance q: a/2 + a/2 sign(q) (1 - exp(-|q| / b)),
+// with ha = a / 2 and ib = 1 / b.
+__device__ __forceinline__ float sdf_sigma(float q, float ha, float ib) {
+  const float m = ha * (1.0f - __expf(-fabsf(q) * ib));
+  return q > 0.0f ? ha + m : (q < 0.0f ? ha - m : ha);
+}
+
 template <int FIELD, bool RGB, bool INT>
 __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
                                             int S, double rS, float t_min, Accum& acc) {
@@ -54,7 +61,15 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
     const float4 a = ip[0], b = ip[1];
     it[0] = a.x; it[1] = a.y; it[2] = a.z; it[3] = a.w; it[4] = b.x; it[5] = b.y; it[6] = b.z; it[7] = b.w;
   }
+  // the paper field (and its SDF variant) evaluates affine forms of x; the corner fields
+  // interpolate corner values
+  constexpr bool kAffine = FIELD == SALF_FIELD_PAPER || FIELD == kFieldSdf;
   float shc[3] = {0.0f, 0.0f, 0.0f};  // view-dependent colour term (paper field)
+  float sdf_ha = 0.0f, sdf_ib = 0.0f;  // SDF variant: a / 2 and 1 / b
+  if (FIELD == kFieldSdf) {
+    sdf_ha = 0.5f * __expf(g[4]);
+    sdf_ib = __expf(-g[5]);
+  }
   if (FIELD == SALF_FIELD_CORNER) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) g[i] = softplus_f(g[i]);
@@ -68,7 +83,7 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
 #pragma unroll
       for (int i = 0; i < 8; ++i) it[i] = sigmoid_f(it[i]);
     }
-  } else if (FIELD == SALF_FIELD_PAPER && RGB) {
+  } else if (kAffine && RGB) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch)
       shc[ch] = fmaf(c[ch][3], sh[0], fmaf(c[ch][4], sh[1], fmaf(c[ch][5], sh[2], c[ch][6] * sh[3])));
@@ -83,7 +98,7 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
     float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-    if (FIELD != SALF_FIELD_PAPER) {
+    if (!kAffine) {
       float w[8];
       corner_weights(u, w);
       sigma = dot8(w, g);
@@ -96,7 +111,8 @@ __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& 
       float x[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
-      sigma = __expf(fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3]))));
+      const float q = fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3])));
+      sigma = FIELD == kFieldSdf ? sdf_sigma(q, sdf_ha, sdf_ib) : __expf(q);
       if (RGB) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
@@ -407,8 +423,9 @@ __global__ __launch_bounds__(kThreads) void raygen_kernel(salf_sensor s, float* 
 // dsigma_j = dL/dtau_j * delta_j, dc_j = gC w_j, di_j = gI w_j; corner logits get these times
 // the trilinear weight and the activation's derivative (softplus' = sigmoid, sigmoid' = s(1-s)).
 // Transmittance is recomputed front to back; the ray stops after the saved number of voxels.
-// PAPER: the field of Eq. 1-2 (raw parameters; ACT is false), else the corner field.
-template <bool RGB, bool INT, bool ACT, bool PAPER>
+// PAPER: the field of Eq. 1-2 (raw parameters; ACT is false), with SDF its density replaced by
+// Eq. 5-6; else the corner field.
+template <bool RGB, bool INT, bool ACT, bool PAPER, bool SDF>
 __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const RenderParams& p = b.fwd;
   int64_t ray;
@@ -458,6 +475,11 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       const float4* gp = reinterpret_cast<const float4*>(s.geo + (int64_t)v * 8);
       const float4 g0 = gp[0];
       sp[0] = g0.x; sp[1] = g0.y; sp[2] = g0.z; sp[3] = g0.w;
+      if (SDF) {
+        const float4 g1 = gp[1];
+        sp[4] = 0.5f * __expf(g1.x);  // a / 2
+        sp[5] = __expf(-g1.y);        // 1 / b
+      }
       if (RGB) {
         const float4* cp = reinterpret_cast<const float4*>(s.rgb + (int64_t)v * 24);
 #pragma unroll
@@ -510,7 +532,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     for (int ch = 0; ch < 3; ++ch) pc[ch][0] = pc[ch][1] = pc[ch][2] = pc[ch][3] = 0.0f;
     for (int k = 0; k < S; ++k) {
       const float fk = (float)k + 0.5f;
-      float u[3], w[8], x[3];
+      float u[3], w[8], x[3], sdq = 0.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
       // the forward's arithmetic, operation for operation, so T and the prefix sums match it
@@ -518,7 +540,8 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       if constexpr (PAPER) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
-        sigma = __expf(fmaf(sp[0], x[0], fmaf(sp[1], x[1], fmaf(sp[2], x[2], sp[3]))));
+        sdq = fmaf(sp[0], x[0], fmaf(sp[1], x[1], fmaf(sp[2], x[2], sp[3])));
+        sigma = SDF ? sdf_sigma(sdq, sp[4], sp[5]) : __expf(sdq);
         if (RGB) {
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch)
@@ -556,7 +579,16 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       if constexpr (PAPER) {
         // ag[0:4]: d/d(density parameters) = dsig sigma (x, 1); aw[ch * 2 + 0:1] hold no corner
         // weights here: aw[0:3] and pc: d/d(colour logit) x (x, 1) per channel, pi likewise
-        const float ds = dsig * sigma;
+        // d(sigma)/d(affine form): sigma itself, or for the SDF density (a / 2b) exp(-|s| / b)
+        float ds;
+        if (SDF) {
+          const float e = __expf(-fabsf(sdq) * sp[5]);
+          ds = dsig * (sp[4] * sp[5] * e);
+          ag[4] = fmaf(dsig, sigma, ag[4]);                       // d/d(log a) = sigma
+          ag[5] = fmaf(dsig, -(sp[4] * sdq * sp[5] * e), ag[5]);  // d/d(log b)
+        } else {
+          ds = dsig * sigma;
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) ag[a] = fmaf(ds, x[a], ag[a]);
         ag[3] += ds;
@@ -591,7 +623,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     // coefficients B times the basis; intensity a, b), zero in the unused slots.
     if constexpr (PAPER) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = i < 4 ? ag[i] : 0.0f;
+      for (int i = 0; i < 8; ++i) red[i * kRedStride + lane] = i < (SDF ? 6 : 4) ? ag[i] : 0.0f;
       if (RGB) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
@@ -637,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     const int rank = __popcll(mine & ((1ull << lane) - 1ull));
     for (int j = rank; j < kRows; j += size) {
       // the paper field's unused record slots get no atomics
-      if (PAPER && (j < 8 ? j >= 4 : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) continue;
+      if (PAPER && (j < 8 ? j >= (SDF ? 6 : 4) : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) continue;
       float sum = 0.0f;
       for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
       float* dst = j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
@@ -727,6 +759,7 @@ hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
   if (field == SALF_FIELD_PAPER) return launch_field<SALF_FIELD_PAPER>(p, blocks, stream);
+  if (field == SALF_FIELD_SDF) return launch_field<kFieldSdf>(p, blocks, stream);
   if (p.scene.act_geo != nullptr) return launch_field<kFieldCornerActivated>(p, blocks, stream);
   return launch_field<SALF_FIELD_CORNER>(p, blocks, stream);
 }
@@ -777,21 +810,26 @@ hipError_t launch_backward(const BackwardParams& b, int field, hipStream_t strea
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
   const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
-  if (field == SALF_FIELD_PAPER) {
-    if (rgb && in) backward_kernel<true, true, false, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false, true><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false, true><<<blocks, kThreads, 0, stream>>>(b);
+  if (field == SALF_FIELD_SDF) {
+    if (rgb && in) backward_kernel<true, true, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
+  } else if (field == SALF_FIELD_PAPER) {
+    if (rgb && in) backward_kernel<true, true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
   } else if (p.scene.act_geo != nullptr) {
-    if (rgb && in) backward_kernel<true, true, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
+    if (rgb && in) backward_kernel<true, true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
   } else {
-    if (rgb && in) backward_kernel<true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    if (rgb && in) backward_kernel<true, true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
   }
   return hipGetLastError();
 }

@@ -82,39 +82,56 @@ def _paper_scene(seed):
     return data
 
 
-@pytest.mark.parametrize("samples", [1, 4])
-def test_paper_field_gradient_matches_oracle(salf, samples):
-    data = _paper_scene(85)
+def _sdf_scene(seed):
+    """A seeded scene for the SDF variant (Eq. 5-6): signed-distance slopes N(0, 0.6^2) and offset
+    N(0, 0.5^2), log a ~ N(0.5, 0.3^2), log b ~ N(-1, 0.3^2); colour and intensity as _paper_scene."""
+    data = _paper_scene(seed)
+    rng = np.random.default_rng(seed + 2)
+    n = data.n
+    geo = np.zeros((n, 8), np.float32)
+    geo[:, :3] = rng.normal(0, 0.6, (n, 3))
+    geo[:, 3] = rng.normal(0, 0.5, n)
+    geo[:, 4] = rng.normal(0.5, 0.3, n)
+    geo[:, 5] = rng.normal(-1.0, 0.3, n)
+    data.z_geo = geo
+    return data
+
+
+@pytest.mark.parametrize("field,samples", [("paper", 1), ("paper", 4), ("sdf", 1), ("sdf", 4)])
+def test_paper_field_gradient_matches_oracle(salf, field, samples):
+    data = _paper_scene(85) if field == "paper" else _sdf_scene(85)
     o, d = synth.random_rays(87, 600, data.origin, data.origin + data.root_dims * data.root_size)
     n = o.shape[0]
     rng = np.random.default_rng(88)
     g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
     g_d, g_o, g_i = (rng.normal(size=n).astype(np.float32) for _ in range(3))
     bg = (0.1, 0.2, 0.3)
-    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    scene = salf.Scene.from_data(data, device=dev(), field=field)
     outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
     saved = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg, samples=samples, outputs=outs)
     grads = {"rgb": to_dev(g_rgb), "depth": to_dev(g_d), "opacity": to_dev(g_o), "intensity": to_dev(g_i)}
     dg, dr, di = salf.render_backward(scene, saved, grads, o=to_dev(o), d=to_dev(d), background=bg,
                                       samples=samples)
     eg, er, ei = oracle.grad_rays(oracle.prepare(data), o, d, RenderOpts(background=bg, samples=samples,
-                                                                          field="paper"),
+                                                                          field=field),
                                   g_rgb, g_d, g_o, g_i)
     dg, dr, di = dg.cpu().numpy(), dr.cpu().numpy(), di.cpu().numpy()
     # the unused record slots receive nothing
-    assert not dg[:, 4:].any() and not dr[:, :, 7].any() and not di[:, 4:].any()
+    used = 6 if field == "sdf" else 4
+    assert not dg[:, used:].any() and not dr[:, :, 7].any() and not di[:, 4:].any()
     _close(dg, eg)
     _close(dr, er)
     _close(di, ei)
 
 
-def test_paper_field_gradient_matches_finite_differences(salf):
+@pytest.mark.parametrize("field", ["paper", "sdf"])
+def test_paper_field_gradient_matches_finite_differences(salf, field):
     """Central differences (eps = 1e-3) of the GPU forward, summed in float64, on a paper-field
-    scene: the parameters are drawn from voxels that at least 8 of the rays hit."""
-    data = _paper_scene(89)
+    (or SDF-variant) scene: the parameters are drawn from voxels that at least 8 of the rays hit."""
+    data = _paper_scene(89) if field == "paper" else _sdf_scene(89)
     lo, hi = data.origin, data.origin + data.root_dims * data.root_size
     o, d = synth.random_rays(90, 4000, lo, hi)
-    scene = salf.Scene.from_data(data, device=dev(), field="paper")
+    scene = salf.Scene.from_data(data, device=dev(), field=field)
     opts = dict(samples=4, t_min=0.0)
     O, D = to_dev(o), to_dev(d)
     n = o.shape[0]
@@ -135,7 +152,7 @@ def test_paper_field_gradient_matches_finite_differences(salf):
     assert cand.size >= 10
     eps = 1e-3
     checks = []
-    for arr, grad, width in ((scene.geo, dg, 4), (scene.rgb, dr, 7)):
+    for arr, grad, width in ((scene.geo, dg, 6 if field == "sdf" else 4), (scene.rgb, dr, 7)):
         for _ in range(12):
             v = int(rng.choice(cand))
             idx = (v,) + ((int(rng.integers(0, 3)),) if arr.dim() == 3 else ()) + (int(rng.integers(0, width)),)

@@ -199,6 +199,32 @@ def test_paper_field_forward(salf):
         check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(samples=S, field="paper")))
 
 
+def test_sdf_field_forward(salf):
+    """The SDF variant (Eq. 5-6): affine signed distance, density a/2 + a/2 sign(s) (1 - e^{-|s|/b})
+    with a = exp(geo[4]), b = exp(geo[5]); colour and intensity as the paper field."""
+    data = synth.random_scene(44, root_dims=(5, 4, 3), max_level=2)
+    rng = np.random.default_rng(45)
+    n = data.n
+    geo = np.zeros((n, 8), F32)
+    geo[:, :3] = rng.normal(0, 0.6, (n, 3))
+    geo[:, 3] = rng.normal(0, 0.5, n)
+    geo[:, 4] = rng.normal(0.5, 0.3, n)
+    geo[:, 5] = rng.normal(-1.0, 0.3, n)
+    rgb = np.zeros((n, 3, 8), F32)
+    rgb[:, :, :7] = rng.normal(0, 0.5, (n, 3, 7))
+    ity = np.zeros((n, 8), F32)
+    ity[:, :4] = rng.normal(0, 0.5, (n, 4))
+    data.z_geo, data.z_rgb, data.z_int = geo, rgb, ity
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev(), field="sdf")
+    o, d = synth.random_rays(46, 600, data.origin, data.origin + data.root_dims * data.root_size)
+    for S in (1, 4):
+        got = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S,
+                          outputs=("rgb", "depth", "opacity", "intensity", "n_hits"))
+        check_outputs(got, oracle.render_rays(ps, o, d, RenderOpts(samples=S, field="sdf")))
+    assert float(got["opacity"].max()) > 0.5
+
+
 def test_tiny_scene_paper_field_camera(salf):
     data = synth.config0_scene()
     rng = np.random.default_rng(44)
