@@ -11,7 +11,8 @@ Layout:
   hitspec   FP32 ray/voxel interval rule, brute force over every voxel
   field     local field evaluation (corner-interpolated mode, the paper's Eq. 1-2 and Eq. 5-6)
   render    samples, compositing (Eq. 3-4) with early termination, per-ray outputs
-  grad      analytic gradient of the composited outputs w.r.t. the raw corner parameters
+  grad      analytic gradient of the composited outputs w.r.t. the raw field parameters
+  refine    densification and pruning of the voxel set (Sec. 3.3)
   sensors   pinhole, equidistant fisheye and spinning-LiDAR rays with rolling shutter
 Everything downstream of the FP32 hit rule is float64.
 """
@@ -19,9 +20,11 @@ from .hitspec import PreparedScene, prepare, ray_frame, box_interval, hit_list, 
 from .field import corner_weights, softplus, sigmoid, corner_field, paper_field, sdf_density, sdf_field, sh_basis
 from .render import RenderOpts, render_rays, render_ray
 from .grad import grad_rays
+from .refine import refine, sigma_max, colour_grad_l1, field_at
 from .sensors import sensor_rays, rodrigues
 
 __all__ = [
+    "refine", "sigma_max", "colour_grad_l1", "field_at",
     "PreparedScene", "prepare", "ray_frame", "box_interval", "hit_list", "hit_lists",
     "corner_weights", "softplus", "sigmoid", "corner_field", "paper_field", "sdf_density", "sdf_field", "sh_basis",
     "RenderOpts", "render_rays", "render_ray", "grad_rays", "sensor_rays", "rodrigues",

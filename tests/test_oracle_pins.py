@@ -627,6 +627,80 @@ def test_p11_oracle_sdf_gradient_matches_central_differences():
             assert abs(fd - grad[idx]) <= 1e-6 * abs(grad[idx]) + 1e-8, (name, idx, fd, grad[idx])
 
 
+# ---------------------------------------------------------------- densification and pruning
+def _refine_scene(field, seed):
+    sc = synth.random_scene(seed, root_dims=(3, 2, 2), max_level=2, fill=0.6)
+    rng = np.random.default_rng(seed + 1)
+    n_v = sc.voxels.shape[0]
+    if field == "corner":
+        return synth.SceneData(**{**sc.__dict__, "z_geo": sc.z_geo.astype(np.float64),
+                                  "z_rgb": sc.z_rgb.astype(np.float64), "z_int": sc.z_int.astype(np.float64)})
+    geo = np.zeros((n_v, 8))
+    geo[:, :4] = rng.normal(0, 0.7, (n_v, 4))
+    if field == "sdf":
+        geo[:, 4], geo[:, 5] = rng.normal(0.5, 0.3, n_v), rng.normal(-1, 0.3, n_v)
+    rgb = np.zeros((n_v, 3, 8))
+    rgb[:, :, :7] = rng.normal(0, 0.7, (n_v, 3, 7))
+    ity = np.zeros((n_v, 8))
+    ity[:, :4] = rng.normal(0, 0.7, (n_v, 4))
+    return synth.SceneData(**{**sc.__dict__, "z_geo": geo, "z_rgb": rgb, "z_int": ity})
+
+
+@pytest.mark.parametrize("field", ["corner", "paper", "sdf"])
+def test_refined_children_carry_the_parent_field(field):
+    """Every child's field equals its parent's at the same world point (random points, float64),
+    children tile their parent, and kept voxels are unchanged."""
+    sc = _refine_scene(field, 41)
+    rng = np.random.default_rng(42)
+    d_rgb = rng.exponential(1.0, sc.z_rgb.shape)
+    out, dec = oracle.refine(sc, d_rgb, grad_threshold=np.median([oracle.colour_grad_l1(g, field) for g in d_rgb]),
+                             alpha_min=0.0, field=field)
+    assert (dec == 8).sum() > 3 and (dec == 1).sum() > 3 and not (dec == 0).any()
+    assert out.n == int(dec.sum())
+    q = 0
+    for v in range(sc.n):
+        lvl, i, j, k = sc.voxels[v]
+        if dec[v] == 1:
+            assert tuple(out.voxels[q]) == (lvl, i, j, k)
+            assert np.array_equal(out.z_geo[q], sc.z_geo[v]) and np.array_equal(out.z_rgb[q], sc.z_rgb[v])
+            q += 1
+            continue
+        for b in range(8):
+            bvec = np.array([(b >> a) & 1 for a in range(3)])
+            assert tuple(out.voxels[q]) == (lvl + 1, 2 * i + bvec[0], 2 * j + bvec[1], 2 * k + bvec[2])
+            for _ in range(4):
+                xc = rng.uniform(-1, 1, 3)
+                xp = xc / 2.0 + (bvec - 0.5)
+                omega = rng.normal(size=3)
+                omega /= np.linalg.norm(omega)
+                sp, cp, ip = oracle.field_at(sc, v, xp, field, omega)
+                sch, cch, ich = oracle.field_at(out, q, xc, field, omega)
+                assert abs(sch - sp) <= 1e-9 * max(1.0, abs(sp))
+                assert np.max(np.abs(cch - cp)) <= 1e-9 and abs(ich - ip) <= 1e-9
+            q += 1
+    assert q == out.n
+
+
+@pytest.mark.parametrize("field", ["corner", "paper", "sdf"])
+def test_pruning_uses_the_largest_opacity_in_the_voxel(field):
+    """sigma_max is the largest density anywhere in the voxel (dense sampling never exceeds it and
+    comes within 1%); pruning removes exactly the voxels whose alpha_max is below alpha_min."""
+    sc = _refine_scene(field, 43)
+    rng = np.random.default_rng(44)
+    g = np.linspace(-1, 1, 9)
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    for v in range(sc.n):
+        smax = oracle.sigma_max(sc.z_geo[v], field)
+        dense = max(oracle.field_at(sc, v, x, field)[0] for x in pts)
+        assert dense <= smax * (1 + 1e-12) and dense >= 0.99 * smax
+    edge = sc.root_size / (1 << sc.voxels[:, 0].astype(np.int64))
+    amax = np.array([1 - math.exp(-oracle.sigma_max(sc.z_geo[v], field) * edge[v]) for v in range(sc.n)])
+    a_min = float(np.median(amax))
+    out, dec = oracle.refine(sc, np.zeros(sc.z_rgb.shape), grad_threshold=1.0, alpha_min=a_min, field=field)
+    assert np.array_equal(dec == 0, amax < a_min)
+    assert out.n == int((amax >= a_min).sum())
+
+
 # ---------------------------------------------------------------- early termination
 def test_early_termination_after_the_voxel_that_crosses_t_min():
     # two voxels in a row along x; the first is nearly opaque (optical depth ~ 30 along x)
