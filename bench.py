@@ -314,6 +314,7 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
     ms = float(np.median(times))
     grad_abs_sum = float(d_geo.abs().sum() + d_rgb.abs().sum())
+    refine = refine_pass(salf, torch, scene, d_rgb, data)
     g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
     g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
     paper = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps)
@@ -325,7 +326,34 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),
             "mrays_s_fwd_bwd": round((n_cam + n_lid) / ms / 1e3, 2), "loss": round(loss, 5),
-            "grad_abs_sum": grad_abs_sum, "paper_field": paper, "sdf_field": sdf}
+            "grad_abs_sum": grad_abs_sum, "paper_field": paper, "sdf_field": sdf, "refine": refine}
+
+
+def refine_pass(salf, torch, scene, d_rgb, data):
+    """Densification and pruning after a training step (Sec. 3.3): split the 5% of touched voxels
+    with the largest colour gradient (L1), prune alpha < 0.001, then build the refined scene (with
+    its dense leaf index).  Wall-clock times; both calls block."""
+    import time
+
+    import numpy as np
+    l1 = d_rgb.abs().sum((1, 2))
+    touched = l1[l1 > 0]
+    thr = float(torch.quantile(touched[:1 << 24].float(), 0.95)) if touched.numel() else 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = scene.refine(d_rgb, thr, 1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    new = salf.Scene(out["voxels"], out["geo"], out["rgb"], out["intensity"], data.origin, data.root_size,
+                     data.root_dims, data.max_level, preactivate=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_in, n_out = scene.n, new.n
+    n_split = int((l1 > thr).sum())
+    new.destroy()
+    return {"voxels_in": n_in, "voxels_out": n_out, "split_threshold_l1": thr, "refine_ms": round((t1 - t0) * 1e3, 3),
+            "rebuild_ms": round((t2 - t1) * 1e3, 3),
+            "note": f"{n_split} voxels over the threshold (those at the finest level stay whole)"}
 
 
 def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, seed=6, field="paper"):

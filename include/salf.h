@@ -197,6 +197,39 @@ salf_status salf_scene_index_size(salf_context* ctx, int32_t scene_id, int32_t m
 salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t max_level, void* d_index,
                                    size_t bytes, void* stream);
 
+/* Densification and pruning of a scene's voxel set (Sec. 3.3), producing the voxels and parameters
+ * of a new scene (the caller builds it with salf_scene_create).  Voxel v is
+ *   pruned  if its largest opacity 1 - exp(-sigma_max edge) is below alpha_min (the paper: 0.001),
+ *           sigma_max being the largest of its 8 corner densities (where every field mode peaks);
+ *   split   else, if level < K and the L1 norm of its colour-field gradient (all 24 colour logits
+ *           of the corner field; rgb[ch][0:3] of the paper and SDF fields) exceeds grad_threshold,
+ *           into its 8 octree-aligned children (child b = bx + 2 by + 4 bz at (2i + bx, 2j + by,
+ *           2k + bz), level + 1), which carry the parent's field exactly: corner logits are the
+ *           inverse activations of the parent's activated field at the child corners; affine
+ *           forms halve their slopes and move their offsets (the colour's into the SH DC term);
+ *   kept    otherwise.
+ * Both decisions are taken in FP64.  Outputs keep the input order, children in the order of b. */
+typedef struct {
+  double grad_threshold;
+  double alpha_min;
+} salf_refine_opts;
+
+/* Bytes of the device work area salf_refine needs for n_voxels.  Errors: INVALID_ARG. */
+salf_status salf_refine_work_size(int64_t n_voxels, size_t* bytes);
+
+/*   d_voxels    device int32 [N, 4], the voxels the scene was built from
+ *   d_grad_rgb  device float [N, 3, 8] dL/d(colour parameters), or NULL (no splits)
+ *   d_work      work area of salf_refine_work_size(N) bytes
+ *   d_*_out     device outputs of `capacity` rows: int32 [cap, 4], float [cap, 8], [cap, 3, 8]
+ *               (NULL if the scene has no colour), [cap, 8] (NULL if it has no intensity)
+ *   *n_out      receives the refined voxel count.  If it exceeds `capacity`, nothing is written
+ *               and OUT_OF_MEMORY is returned (call again with enough rows; capacity 0 queries).
+ * Blocks until done on `stream`.  Errors: INVALID_ARG, NOT_FOUND, OUT_OF_MEMORY, DEVICE. */
+salf_status salf_refine(salf_context* ctx, int32_t scene_id, const int32_t* d_voxels, const float* d_grad_rgb,
+                        const salf_refine_opts* opts, void* d_work, size_t work_bytes, int32_t* d_voxels_out,
+                        float* d_geo_out, float* d_rgb_out, float* d_int_out, int64_t capacity, int64_t* n_out,
+                        void* stream);
+
 /* Forget a scene.  Its workspace and parameter buffers may be freed by the caller once the
  * work that used them has completed.  Errors: NOT_FOUND. */
 salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id);

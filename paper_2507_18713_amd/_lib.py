@@ -18,12 +18,17 @@ FIELD_CORNER, FIELD_PAPER, FIELD_SDF = 0, 1, 2
 SCENE_PREACTIVATE = 1
 SCHEDULE_NONE, SCHEDULE_BUILD, SCHEDULE_REUSE = 0, 1, 2
 MAX_INDEX_LEVEL = 6  # SALF_MAX_INDEX_LEVEL
+ERR_OUT_OF_MEMORY = -2
 PINHOLE, FISHEYE_EQUIDISTANT, LIDAR_SPINNING = 0, 1, 2
 
 
 class SceneDesc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("root_size", C.c_double), ("root_dims", C.c_int32 * 3),
                 ("max_level", C.c_int32), ("field", C.c_int32), ("flags", C.c_int32)]
+
+
+class RefineOpts(C.Structure):
+    _fields_ = [("grad_threshold", C.c_double), ("alpha_min", C.c_double)]
 
 
 class SceneStats(C.Structure):
@@ -82,6 +87,10 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                       C.POINTER(C.c_int32)]),
     "salf_scene_refresh": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "salf_refine_work_size": (C.c_int32, [C.c_int64, C.POINTER(C.c_size_t)]),
+    "salf_refine": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(RefineOpts), C.c_void_p,
+                                C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.POINTER(C.c_int64), C.c_void_p]),
     "salf_scene_index_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "salf_scene_build_index": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "salf_scene_get_stats": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SceneStats)]),

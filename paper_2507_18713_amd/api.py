@@ -165,6 +165,37 @@ class Scene:
         return cls(vox, geo, col, ity, data.origin, data.root_size, data.root_dims, data.max_level, field,
                    preactivate, DEFAULT_INDEX_LEVEL if index_level is None else index_level)
 
+    def refine(self, grad_rgb: Optional[torch.Tensor], grad_threshold: float, alpha_min: float = 1e-3) -> dict:
+        """Densify and prune (Sec. 3.3; salf_refine): voxels whose largest opacity is below
+        alpha_min are dropped, voxels whose colour-field gradient (L1) exceeds grad_threshold are
+        split into 8 children carrying their field, the rest kept.  Returns the new scene's device
+        arrays {voxels, geo, rgb, intensity} (build it with Scene(...))."""
+        dev = self.device
+        if grad_rgb is not None:
+            _check_dev(grad_rgb, torch.float32, dev, "grad_rgb", (self.n, 3, 8))
+        opts = _lib.RefineOpts(float(grad_threshold), float(alpha_min))
+        wb = C.c_size_t()
+        call("salf_refine_work_size", self.n, C.byref(wb))
+        work = torch.empty(max(int(wb.value), 256), dtype=torch.uint8, device=dev)
+        n_out = C.c_int64()
+        g = _ptr(grad_rgb) if grad_rgb is not None else None
+        st = _lib.lib().salf_refine(self.ctx.handle, self.id, _ptr(self._voxels), g, C.byref(opts), _ptr(work),
+                                    int(work.numel()), None, None, None, None, 0, C.byref(n_out), _stream(dev))
+        if st not in (0, _lib.ERR_OUT_OF_MEMORY):
+            call("salf_refine", self.ctx.handle, self.id, _ptr(self._voxels), g, C.byref(opts), _ptr(work),
+                 int(work.numel()), None, None, None, None, 0, C.byref(n_out), _stream(dev))
+        m = int(n_out.value)
+        out = {"voxels": torch.empty((m, 4), dtype=torch.int32, device=dev),
+               "geo": torch.empty((m, 8), dtype=torch.float32, device=dev),
+               "rgb": torch.empty((m, 3, 8), dtype=torch.float32, device=dev) if self.rgb is not None else None,
+               "intensity": torch.empty((m, 8), dtype=torch.float32, device=dev) if self.intensity is not None else None}
+        if m > 0:
+            call("salf_refine", self.ctx.handle, self.id, _ptr(self._voxels), g, C.byref(opts), _ptr(work),
+                 int(work.numel()), _ptr(out["voxels"]), _ptr(out["geo"]),
+                 _ptr(out["rgb"]) if out["rgb"] is not None else None,
+                 _ptr(out["intensity"]) if out["intensity"] is not None else None, m, C.byref(n_out), _stream(dev))
+        return out
+
     def stats(self) -> dict:
         s = _lib.SceneStats()
         call("salf_scene_get_stats", self.ctx.handle, self.id, C.byref(s))

@@ -436,6 +436,45 @@ salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t 
   return attach_index(ctx, scene_id, sc, d_boff, d_entries);
 }
 
+salf_status salf_refine_work_size(int64_t n_voxels, size_t* bytes) {
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_voxels < 0 || n_voxels > ((int64_t)1 << 30)) return set_error(SALF_ERR_INVALID_ARG, "n_voxels out of range");
+  *bytes = refine_work_bytes(n_voxels);
+  return SALF_OK;
+}
+
+salf_status salf_refine(salf_context* ctx, int32_t scene_id, const int32_t* d_voxels, const float* d_grad_rgb,
+                        const salf_refine_opts* opts, void* d_work, size_t work_bytes, int32_t* d_voxels_out,
+                        float* d_geo_out, float* d_rgb_out, float* d_int_out, int64_t capacity, int64_t* n_out,
+                        void* stream) {
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
+  if (st) return st;
+  if (!opts || !n_out) return set_error(SALF_ERR_INVALID_ARG, "opts and n_out are required");
+  if (!(opts->grad_threshold >= 0.0) || !(opts->alpha_min >= 0.0) || !(opts->alpha_min <= 1.0))
+    return set_error(SALF_ERR_INVALID_ARG, "grad_threshold must be >= 0 and alpha_min in [0, 1]");
+  if (capacity < 0) return set_error(SALF_ERR_INVALID_ARG, "capacity must be >= 0");
+  const int64_t n = sc.n;
+  if (n > 0 && !d_voxels) return set_error(SALF_ERR_INVALID_ARG, "voxels are required");
+  if (n > 0 && (!d_work || work_bytes < refine_work_bytes(n)))
+    return set_error(SALF_ERR_INVALID_ARG, "work area must hold %zu bytes", refine_work_bytes(n));
+  if (capacity > 0 && (!d_voxels_out || !d_geo_out || (sc.view.rgb && !d_rgb_out) || (sc.view.inten && !d_int_out)))
+    return set_error(SALF_ERR_INVALID_ARG, "an output the scene needs is NULL");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", ctx->device);
+  int64_t total = 0;
+  if ((st = check_hip(launch_refine(sc.view, sc.desc, n, d_voxels, d_grad_rgb, opts->grad_threshold, opts->alpha_min,
+                                    d_work, d_voxels_out, d_geo_out, d_rgb_out, d_int_out, capacity, &total,
+                                    (hipStream_t)stream),
+                      "refine")))
+    return st;
+  *n_out = total;
+  if (total > capacity)
+    return set_error(SALF_ERR_OUT_OF_MEMORY, "the refined scene has %lld voxels, the outputs hold %lld",
+                     (long long)total, (long long)capacity);
+  return SALF_OK;
+}
+
 salf_status salf_scene_destroy(salf_context* ctx, int32_t scene_id) {
   if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
   std::lock_guard<std::mutex> lk(ctx->mu);

@@ -44,6 +44,15 @@ struct BuildCounters {
 hipError_t launch_activate(const float* geo, const float* rgb, const float* inten, int64_t n_voxels, float* act_geo,
                            float* act_rgb, float* act_int, hipStream_t stream);
 
+// Densification and pruning (Sec. 3.3) of a scene's n voxels into caller buffers of `capacity`
+// rows: *total receives the refined count; nothing is written when it exceeds the capacity.  work:
+// refine_work_bytes(n) bytes.  Blocks on `stream`.
+size_t refine_work_bytes(int64_t n);
+hipError_t launch_refine(const SceneView& v, const salf_scene_desc& d, int64_t n, const int32_t* vox,
+                         const float* grad_rgb, double grad_threshold, double alpha_min, void* work,
+                         int32_t* vox_out, float* geo_out, float* rgb_out, float* int_out, int64_t capacity,
+                         int64_t* total, hipStream_t stream);
+
 // Dense leaf indexes of a built scene: boff[cell] is the first entry of the cell's index or -1.
 hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
                              hipStream_t stream);

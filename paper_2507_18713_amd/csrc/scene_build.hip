@@ -458,6 +458,193 @@ hipError_t launch_activate(const float* geo, const float* rgb, const float* inte
   return hipGetLastError();
 }
 
+namespace {
+// ---- densification and pruning (Sec. 3.3)
+struct RefineArgs {
+  const int32_t* vox;       // [n, 4] (l, i, j, k)
+  const float* geo;         // [n, 8]
+  const float* rgb;         // [n, 3, 8] or null
+  const float* inten;       // [n, 8] or null
+  const float* grad_rgb;    // [n, 3, 8] or null (no splits)
+  int64_t n;
+  int32_t K, field;
+  double s0, grad_threshold, alpha_min;
+};
+
+__device__ __forceinline__ double softplus64(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+__device__ __forceinline__ double sigmoid64(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+// Largest density of a voxel: the largest corner density (trilinear of non-negative corner
+// values; exp of an affine form; Eq. 6, monotone in an affine signed distance).
+__device__ double sigma_max64(const float* g, int field) {
+  double m = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    double sig;
+    if (field == SALF_FIELD_CORNER) {
+      sig = softplus64(g[c]);
+    } else {
+      const double q = (c & 1 ? 1.0 : -1.0) * g[0] + (c & 2 ? 1.0 : -1.0) * g[1] + (c & 4 ? 1.0 : -1.0) * g[2] + g[3];
+      if (field == SALF_FIELD_SDF) {
+        const double a = exp((double)g[4]), b = exp((double)g[5]);
+        const double e = 1.0 - exp(-fabs(q) / b);
+        sig = a / 2.0 + a / 2.0 * (q > 0.0 ? e : (q < 0.0 ? -e : 0.0));
+      } else {
+        sig = exp(q);
+      }
+    }
+    m = fmax(m, sig);
+  }
+  return m;
+}
+
+// Output rows of voxel v: 0 (pruned), 1 (kept) or 8 (split), in float64 as the decision's
+// definition states them.
+__global__ void refine_count_kernel(RefineArgs a, int32_t* count) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int lvl = a.vox[v * 4];
+  const double edge = a.s0 / (double)(1 << lvl);
+  const double alpha = -expm1(-sigma_max64(a.geo + v * 8, a.field) * edge);
+  int32_t c = 1;
+  if (alpha < a.alpha_min) {
+    c = 0;
+  } else if (lvl < a.K && a.grad_rgb != nullptr) {
+    double l1 = 0.0;
+    for (int ch = 0; ch < 3; ++ch)
+      for (int i = 0; i < (a.field == SALF_FIELD_CORNER ? 8 : 3); ++i) l1 += fabs((double)a.grad_rgb[v * 24 + ch * 8 + i]);
+    if (l1 > a.grad_threshold) c = 8;
+  }
+  count[v] = c;
+}
+
+__device__ __forceinline__ float logit64(double q, double q1) { return (float)(log(q) - log(q1)); }
+
+// Writes each voxel's output rows at its offset (offs: exclusive scan of the counts, total: their
+// sum).  Children carry the parent's field exactly: corner logits are the inverse activations of
+// the parent's activated field at the child corners; affine forms halve their slopes and move
+// their offsets (the colour's into the SH DC coefficient, times 1 / C0).
+__global__ void refine_emit_kernel(RefineArgs a, const int32_t* offs, int64_t total, int32_t* vox_out,
+                                   float* geo_out, float* rgb_out, float* int_out) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= a.n) return;
+  const int64_t o = offs[v];
+  const int64_t c = (v + 1 < a.n ? (int64_t)offs[v + 1] : total) - o;
+  const int32_t* vx = a.vox + v * 4;
+  const float* g = a.geo + v * 8;
+  const float* r = a.rgb ? a.rgb + v * 24 : nullptr;
+  const float* it = a.inten ? a.inten + v * 8 : nullptr;
+  if (c == 1) {
+    for (int t = 0; t < 4; ++t) vox_out[o * 4 + t] = vx[t];
+    for (int t = 0; t < 8; ++t) geo_out[o * 8 + t] = g[t];
+    if (r && rgb_out) for (int t = 0; t < 24; ++t) rgb_out[o * 24 + t] = r[t];
+    if (it && int_out) for (int t = 0; t < 8; ++t) int_out[o * 8 + t] = it[t];
+    return;
+  }
+  if (c != 8) return;
+  for (int b = 0; b < 8; ++b) {
+    const int64_t q = o + b;
+    const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+    vox_out[q * 4 + 0] = vx[0] + 1;
+    vox_out[q * 4 + 1] = 2 * vx[1] + bx;
+    vox_out[q * 4 + 2] = 2 * vx[2] + by;
+    vox_out[q * 4 + 3] = 2 * vx[3] + bz;
+    const double ob[3] = {bx - 0.5, by - 0.5, bz - 0.5};
+    if (a.field == SALF_FIELD_CORNER) {
+      for (int k = 0; k < 8; ++k) {
+        // child corner k in the parent's unit coordinates u = (x_p + 1) / 2 (0, 1/2 or 1)
+        double w[8];
+        const double u[3] = {((k & 1 ? 1.0 : -1.0) / 2.0 + ob[0] + 1.0) / 2.0,
+                             ((k & 2 ? 1.0 : -1.0) / 2.0 + ob[1] + 1.0) / 2.0,
+                             ((k & 4 ? 1.0 : -1.0) / 2.0 + ob[2] + 1.0) / 2.0};
+        for (int p = 0; p < 8; ++p)
+          w[p] = (p & 1 ? u[0] : 1.0 - u[0]) * (p & 2 ? u[1] : 1.0 - u[1]) * (p & 4 ? u[2] : 1.0 - u[2]);
+        double y = 0.0;
+        for (int p = 0; p < 8; ++p) y += w[p] * softplus64(g[p]);
+        geo_out[q * 8 + k] = (float)log(expm1(y));
+        if (r && rgb_out) {
+          for (int ch = 0; ch < 3; ++ch) {
+            double s1 = 0.0, s0 = 0.0;  // the interpolated value and its complement, each accurate
+            for (int p = 0; p < 8; ++p) {
+              s1 += w[p] * sigmoid64(r[ch * 8 + p]);
+              s0 += w[p] * sigmoid64(-(double)r[ch * 8 + p]);
+            }
+            rgb_out[q * 24 + ch * 8 + k] = logit64(s1, s0);
+          }
+        }
+        if (it && int_out) {
+          double s1 = 0.0, s0 = 0.0;
+          for (int p = 0; p < 8; ++p) {
+            s1 += w[p] * sigmoid64(it[p]);
+            s0 += w[p] * sigmoid64(-(double)it[p]);
+          }
+          int_out[q * 8 + k] = logit64(s1, s0);
+        }
+      }
+    } else {
+      constexpr double kC0 = 0.28209479177387814;
+      for (int t = 0; t < 8; ++t) geo_out[q * 8 + t] = g[t];
+      geo_out[q * 8 + 0] = (float)(g[0] / 2.0);
+      geo_out[q * 8 + 1] = (float)(g[1] / 2.0);
+      geo_out[q * 8 + 2] = (float)(g[2] / 2.0);
+      geo_out[q * 8 + 3] = (float)(g[3] + g[0] * ob[0] + g[1] * ob[1] + g[2] * ob[2]);
+      if (r && rgb_out) {
+        for (int ch = 0; ch < 3; ++ch) {
+          const float* rc = r + ch * 8;
+          float* oc = rgb_out + q * 24 + ch * 8;
+          for (int t = 0; t < 8; ++t) oc[t] = rc[t];
+          oc[0] = (float)(rc[0] / 2.0);
+          oc[1] = (float)(rc[1] / 2.0);
+          oc[2] = (float)(rc[2] / 2.0);
+          oc[3] = (float)(rc[3] + (rc[0] * ob[0] + rc[1] * ob[1] + rc[2] * ob[2]) / kC0);
+        }
+      }
+      if (it && int_out) {
+        for (int t = 0; t < 8; ++t) int_out[q * 8 + t] = it[t];
+        int_out[q * 8 + 0] = (float)(it[0] / 2.0);
+        int_out[q * 8 + 1] = (float)(it[1] / 2.0);
+        int_out[q * 8 + 2] = (float)(it[2] / 2.0);
+        int_out[q * 8 + 3] = (float)(it[3] + it[0] * ob[0] + it[1] * ob[1] + it[2] * ob[2]);
+      }
+    }
+  }
+}
+}  // namespace
+
+size_t refine_work_bytes(int64_t n) { return ((size_t)(n + scan_temp(n > 0 ? n : 1)) * 4 + 255) / 256 * 256; }
+
+hipError_t launch_refine(const SceneView& v, const salf_scene_desc& d, int64_t n, const int32_t* vox,
+                         const float* grad_rgb, double grad_threshold, double alpha_min, void* work,
+                         int32_t* vox_out, float* geo_out, float* rgb_out, float* int_out, int64_t capacity,
+                         int64_t* total, hipStream_t stream) {
+  *total = 0;
+  if (n <= 0) return hipSuccess;
+  RefineArgs a;
+  a.vox = vox;
+  a.geo = v.geo;
+  a.rgb = v.rgb;
+  a.inten = v.inten;
+  a.grad_rgb = grad_rgb;
+  a.n = n;
+  a.K = d.max_level;
+  a.field = d.field;
+  a.s0 = d.root_size;
+  a.grad_threshold = grad_threshold;
+  a.alpha_min = alpha_min;
+  int32_t* count = (int32_t*)work;
+  refine_count_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(a, count);
+  int32_t last[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(&last[0], count + n - 1, 4, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  launch_scan(count, n, count + n, stream);
+  if ((e = hipMemcpyAsync(&last[1], count + n - 1, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  *total = (int64_t)last[0] + last[1];
+  if (*total > capacity) return hipSuccess;
+  refine_emit_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(a, count, *total, vox_out, geo_out, rgb_out, int_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipStreamSynchronize(stream);
+}
+
 hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
                              hipStream_t stream) {
   for (int64_t c0 = 0; c0 < n_root; c0 += (int64_t)1 << 30) {

@@ -407,3 +407,43 @@ def test_preactivated_scene_matches_oracle_and_refreshes(salf):
     check_outputs(fresh, oracle.render_rays(oracle.prepare(data2), o, d, RenderOpts()))
     with pytest.raises(salf.SalfError, match="corner field only"):
         salf.Scene.from_data(data, device=dev(), field="paper", preactivate=True)
+
+
+@pytest.mark.parametrize("field", ["corner", "paper", "sdf"])
+def test_refine_matches_oracle(salf, field):
+    """Densification and pruning (Sec. 3.3) on the GPU against the oracle: the same decisions and
+    voxel list bit for bit, child parameters within 1e-5 (FP32 outputs of FP64 arithmetic)."""
+    data = synth.random_scene(51, root_dims=(5, 4, 3), max_level=3)
+    rng = np.random.default_rng(52)
+    n = data.n
+    if field != "corner":
+        geo = np.zeros((n, 8), F32)
+        geo[:, :4] = rng.normal(0, 0.7, (n, 4))
+        if field == "sdf":
+            geo[:, 4], geo[:, 5] = rng.normal(0.5, 0.3, n), rng.normal(-1, 0.3, n)
+        rgb = np.zeros((n, 3, 8), F32)
+        rgb[:, :, :7] = rng.normal(0, 0.7, (n, 3, 7))
+        ity = np.zeros((n, 8), F32)
+        ity[:, :4] = rng.normal(0, 0.7, (n, 4))
+        data.z_geo, data.z_rgb, data.z_int = geo, rgb, ity
+    grad = rng.exponential(1.0, (n, 3, 8)).astype(F32)
+    l1 = np.array([oracle.colour_grad_l1(g, field) for g in grad])
+    edge = data.root_size / (1 << data.voxels[:, 0].astype(np.int64))
+    amax = np.array([1 - np.exp(-oracle.sigma_max(data.z_geo[v], field) * edge[v]) for v in range(n)])
+    thr, a_min = float(np.quantile(l1, 0.6)), float(np.quantile(amax, 0.2))
+    scene = salf.Scene.from_data(data, device=dev(), field=field)
+    got = scene.refine(to_dev(grad), thr, a_min)
+    ref, dec = oracle.refine(data, grad, thr, a_min, field)
+    assert (dec == 0).sum() > 10 and (dec == 8).sum() > 10 and (dec == 1).sum() > 10
+    assert np.array_equal(got["voxels"].cpu().numpy(), ref.voxels)
+    for k, r in (("geo", ref.z_geo), ("rgb", ref.z_rgb), ("intensity", ref.z_int)):
+        g = got[k].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(g - r) / (1.0 + np.abs(r))) <= 1e-5, k
+    # the refined set is a valid scene: it builds, and its parameters render
+    data2 = synth.SceneData(**{**data.__dict__, "voxels": ref.voxels, "z_geo": got["geo"].cpu().numpy(),
+                               "z_rgb": got["rgb"].cpu().numpy(), "z_int": got["intensity"].cpu().numpy()})
+    scene2 = salf.Scene.from_data(data2, device=dev(), field=field)
+    assert scene2.stats()["n_voxels"] == ref.n
+    # no gradient: nothing splits; alpha_min 0: nothing is pruned
+    same = scene.refine(None, 0.0, 0.0)
+    assert torch.equal(same["voxels"], to_dev(data.voxels, torch.int32)) and torch.equal(same["geo"], to_dev(data.z_geo))
