@@ -502,7 +502,9 @@ __device__ double sigma_max64(const float* g, int field) {
 __global__ void refine_count_kernel(RefineArgs a, int32_t* count) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= a.n) return;
-  const int lvl = a.vox[v * 4];
+  // the caller's voxels are those the scene was built from (levels in [0, K]); clamp anyway so
+  // that a wrong array cannot shift out of range
+  const int lvl = min(max(a.vox[v * 4], 0), a.K);
   const double edge = a.s0 / (double)(1 << lvl);
   const double alpha = -expm1(-sigma_max64(a.geo + v * 8, a.field) * edge);
   int32_t c = 1;
