@@ -252,6 +252,44 @@ def test_empty_scene_and_misses(salf):
     z = torch.zeros((0, 3), device=dev())
     got = salf.render(scene, o=z, d=z, outputs=("rgb",))
     assert got["rgb"].shape == (0, 3)
+    # refining an empty scene gives an empty scene
+    out = scene.refine(None, 0.0)
+    assert out["voxels"].shape == (0, 4) and out["geo"].shape == (0, 8)
+
+
+def test_refine_and_index_edge_cases(salf):
+    from paper_2507_18713_amd._lib import RefineOpts, call
+    # a scene of level-0 voxels only (K = 0): no octree cells, so the index is empty, and no voxel
+    # can split
+    data = synth.random_scene(61, root_dims=(4, 3, 3), max_level=0, fill=0.5)
+    scene = salf.Scene.from_data(data, device=dev(), index_level=0)
+    o, d = synth.random_rays(62, 400, data.origin, data.origin + data.root_dims * data.root_size)
+    ref = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    scene.build_index(4)
+    got = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    assert torch.equal(got["rgb"], ref["rgb"]) and torch.equal(got["n_hits"], ref["n_hits"])
+    big = torch.full((data.n, 3, 8), 1e3, device=dev())
+    out = scene.refine(big, 0.0, 0.0)
+    assert torch.equal(out["voxels"], to_dev(data.voxels, torch.int32))
+    # argument errors
+    nb = ctypes.c_size_t()
+    call("salf_refine_work_size", scene.n, ctypes.byref(nb))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=dev())
+    n_out = ctypes.c_int64()
+    stream = torch.cuda.current_stream().cuda_stream
+    for bad in (RefineOpts(-1.0, 0.0), RefineOpts(0.0, 2.0), RefineOpts(float("nan"), 0.0)):
+        with pytest.raises(salf.SalfError, match="grad_threshold"):
+            call("salf_refine", scene.ctx.handle, scene.id, scene._voxels.data_ptr(), None, ctypes.byref(bad),
+                 work.data_ptr(), int(work.numel()), None, None, None, None, 0, ctypes.byref(n_out), stream)
+    with pytest.raises(salf.SalfError, match="work area"):
+        call("salf_refine", scene.ctx.handle, scene.id, scene._voxels.data_ptr(), None,
+             ctypes.byref(RefineOpts(0.0, 0.0)), work.data_ptr(), 16, None, None, None, None, 0,
+             ctypes.byref(n_out), stream)
+    with pytest.raises(salf.SalfError, match="OUT_OF_MEMORY"):
+        call("salf_refine", scene.ctx.handle, scene.id, scene._voxels.data_ptr(), None,
+             ctypes.byref(RefineOpts(0.0, 0.0)), work.data_ptr(), int(work.numel()), None, None, None, None, 0,
+             ctypes.byref(n_out), stream)
+    assert n_out.value == data.n
 
 
 def test_invalid_rays_render_background(salf):
