@@ -422,7 +422,7 @@ salf_status salf_server_create(salf_context* ctx, const salf_server_opts* opts, 
 
 /* Queue a render of `sensor` on scene `scene_id` (corner field) with `opts`.  Non-blocking; the
  * scene must stay alive until the request completes.  *ticket identifies the request.
- * Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper field), BUDGET (its outputs alone exceed the
+ * Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper or SDF field), BUDGET (its outputs alone exceed the
  * pool). */
 salf_status salf_server_submit(salf_server* server, int32_t scene_id, const salf_sensor* sensor,
                                const salf_render_opts* opts, uint32_t outputs, uint64_t* ticket);
