@@ -101,9 +101,10 @@ def test_admission_respects_the_budget_in_order(salf, scenes):
     srv.close()
 
 
-def test_paper_field_scene_is_refused(salf):
+@pytest.mark.parametrize("field", ["paper", "sdf"])
+def test_paper_field_scene_is_refused(salf, field):
     data = synth.random_scene(203)
-    sc = salf.Scene.from_data(data, device=dev(), field="paper")
+    sc = salf.Scene.from_data(data, device=dev(), field=field)
     srv = salf.Server(pool_bytes=1 << 20, device=dev())
     with pytest.raises(salf.SalfError, match="UNSUPPORTED"):
         srv.submit(sc, synth.pinhole(8, 8, 60.0, np.eye(3), (0, 0, -5)))
