@@ -13,6 +13,7 @@ Layout:
   render    samples, compositing (Eq. 3-4) with early termination, per-ray outputs
   grad      analytic gradient of the composited outputs w.r.t. the raw field parameters
   refine    densification and pruning of the voxel set (Sec. 3.3)
+  composite a static scene with dynamic actors placed by rigid poses (merged traversal)
   sensors   pinhole, equidistant fisheye and spinning-LiDAR rays with rolling shutter
 Everything downstream of the FP32 hit rule is float64.
 """
@@ -21,9 +22,11 @@ from .field import corner_weights, softplus, sigmoid, corner_field, paper_field,
 from .render import RenderOpts, render_rays, render_ray
 from .grad import grad_rays
 from .refine import refine, sigma_max, colour_grad_l1, field_at
+from .composite import actor_ray, composite_rays
 from .sensors import sensor_rays, rodrigues
 
 __all__ = [
+    "actor_ray", "composite_rays",
     "refine", "sigma_max", "colour_grad_l1", "field_at",
     "PreparedScene", "prepare", "ray_frame", "box_interval", "hit_list", "hit_lists",
     "corner_weights", "softplus", "sigmoid", "corner_field", "paper_field", "sdf_density", "sdf_field", "sh_basis",

@@ -701,6 +701,43 @@ def test_pruning_uses_the_largest_opacity_in_the_voxel(field):
     assert out.n == int((amax >= a_min).sum())
 
 
+# ---------------------------------------------------------------- dynamic actors
+def test_composite_without_actors_is_the_plain_render():
+    sc = synth.random_scene(71, root_dims=(3, 3, 2), max_level=2)
+    ps = oracle.prepare(sc)
+    o, d = synth.random_rays(72, 60, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    opts = RenderOpts(background=(0.1, 0.2, 0.3))
+    a, b = oracle.composite_rays(ps, [], o, d, opts), oracle.render_rays(ps, o, d, opts)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_composite_equals_the_merged_scene():
+    """Moving the voxels of a slab of root cells into an actor (its own grid over that slab, placed
+    with the identity pose) renders like the original scene: the actor's box splits the static walk
+    exactly where the slab's voxels are (up to the rounding of the actor grid's own frame)."""
+    sc = synth.random_scene(73, root_dims=(6, 3, 3), max_level=2, fill=0.7)
+    lvl = sc.voxels[:, 0].astype(np.int64)
+    cell_x = sc.voxels[:, 1].astype(np.int64) >> lvl      # root cell index along x
+    inside = (cell_x >= 2) & (cell_x < 4)
+    static = sc.subset(~inside)
+    act = sc.subset(inside)
+    act.voxels = act.voxels.copy()
+    act.voxels[:, 1] -= (2 << act.voxels[:, 0]).astype(np.int32)
+    act.origin = np.asarray(sc.origin, np.float64) + np.array([2 * sc.root_size, 0.0, 0.0])
+    act.root_dims = np.array([2, sc.root_dims[1], sc.root_dims[2]])
+    assert static.n > 20 and act.n > 20
+    o, d = synth.random_rays(74, 300, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    opts = RenderOpts(background=(0.1, 0.2, 0.3))
+    got = oracle.composite_rays(oracle.prepare(static), [(oracle.prepare(act), np.eye(3), np.zeros(3))], o, d, opts)
+    ref = oracle.render_rays(oracle.prepare(sc), o, d, opts)
+    assert np.mean(got["n_hits"] != ref["n_hits"]) <= 0.01
+    same = got["n_hits"] == ref["n_hits"]
+    for k in ("rgb", "depth", "opacity", "intensity"):
+        assert np.max(np.abs(got[k][same] - ref[k][same])) <= 1e-5, k
+    assert int(ref["n_hits"].sum()) > 300
+
+
 # ---------------------------------------------------------------- early termination
 def test_early_termination_after_the_voxel_that_crosses_t_min():
     # two voxels in a row along x; the first is nearly opaque (optical depth ~ 30 along x)
