@@ -343,6 +343,32 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
                         const salf_rays* rays, const salf_render_opts* opts, const salf_outputs* out,
                         void* stream);
 
+/* ------------------------------------------------------------------ dynamic actors */
+/* An actor: a scene in its own canonical frame placed by a rigid pose, a world point p being the
+ * actor point R^T (p - t) (R row-major, orthonormal). */
+typedef struct {
+  int32_t scene_id;
+  float R[9];
+  float t[3];
+} salf_actor;
+#define SALF_MAX_ACTORS 7
+
+/* Render a static scene together with up to SALF_MAX_ACTORS actors (the simulator's merged
+ * traversal of a background and its moving actors, Sec. 4.1).  Per ray, each actor's root grid is met in
+ * the actor's frame, where the ray is (R^T (o - t), R^T d) formed in FP32 in that order, every
+ * operation rounded ((R[i] p0 + R[3 + i] p1) + R[6 + i] p2 per component); a rigid map keeps
+ * the ray parameter, so every scene's intervals and depths share it.  The ray walks the static
+ * scene up to the first actor box it meets, that actor over its box, the static scene up to the
+ * next box, and so on to t_far, compositing every hit in that order as salf_render does.  Actors
+ * must not overlap one another or static voxels (the background holds no voxel where an actor
+ * is); otherwise hits are composited in that piecewise order, not sorted.  All scenes must use
+ * the corner field, all with SALF_SCENE_PREACTIVATE or none, and hold every requested channel.
+ * `sensor`/`rays`, `opts` (its schedule is built from the static scene) and `out` as salf_render.
+ * Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (another field), DEVICE. */
+salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, int32_t n_actors,
+                                  const salf_actor* actors, const salf_sensor* sensor, const salf_rays* rays,
+                                  const salf_render_opts* opts, const salf_outputs* out, void* stream);
+
 /* The voxels each explicit ray hits, front to back, with no early termination:
  *   d_counts int32 [n]: total hits of the ray (may exceed max_hits)
  *   d_ids int32 [n, max_hits]: voxel ids (upload index); d_t_in, d_t_out float [n, max_hits]

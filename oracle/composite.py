@@ -1,5 +1,5 @@
-"""Rendering a static scene with dynamic actors (the simulator's merged traversal), float64 —
-test infrastructure.
+"""Rendering a static scene with dynamic actors (the simulator's merged traversal, Sec. 4.1),
+float64 — test infrastructure.
 
 Each actor is a scene in its own canonical frame, placed by a rigid pose (R, t): a world point p is
 the actor point R^T (p - t).  A ray (o, d) meets an actor in the actor frame, where it is

@@ -31,6 +31,10 @@ class RefineOpts(C.Structure):
     _fields_ = [("grad_threshold", C.c_double), ("alpha_min", C.c_double)]
 
 
+class Actor(C.Structure):
+    _fields_ = [("scene_id", C.c_int32), ("R", C.c_float * 9), ("t", C.c_float * 3)]
+
+
 class SceneStats(C.Structure):
     _fields_ = [("n_voxels", C.c_int64), ("n_nodes", C.c_int64), ("n_root_cells", C.c_int64),
                 ("n_occupied_roots", C.c_int64), ("workspace_bytes", C.c_size_t)]
@@ -91,6 +95,8 @@ SIGNATURES = {
     "salf_refine": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(RefineOpts), C.c_void_p,
                                 C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                 C.POINTER(C.c_int64), C.c_void_p]),
+    "salf_render_composite": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p]),
     "salf_scene_index_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "salf_scene_build_index": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "salf_scene_get_stats": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SceneStats)]),

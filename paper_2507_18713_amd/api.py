@@ -338,6 +338,45 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     return res
 
 
+def render_composite(scene: Scene, actors, sensor: Optional[dict] = None, o: Optional[torch.Tensor] = None,
+                     d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6,
+                     background=(0.0, 0.0, 0.0), outputs: Iterable[str] = ("rgb", "depth", "opacity"),
+                     t_near: float = 0.0, t_far: float = math.inf, image_width: int = 0,
+                     schedule=True) -> Dict[str, torch.Tensor]:
+    """Render a static scene with dynamic actors (salf_render_composite): actors is a list of
+    (Scene, R [3, 3], t [3]), a world point p being the actor point R^T (p - t).  Other arguments
+    and the result as render()."""
+    dev = scene.device
+    outputs = tuple(outputs)
+    for k in outputs:
+        if k not in OUTPUT_NAMES:
+            raise ValueError(f"unknown output {k}")
+    sen = rays = None
+    if sensor is not None:
+        sen = sensor_struct(sensor)
+        n = ray_count(sensor)
+    else:
+        rays = _rays_struct(o, d, t_near, t_far, dev, image_width)
+        n = int(rays.n)
+    res = {}
+    for k in outputs:
+        shape = (n, 3) if k == "rgb" else (n,)
+        res[k] = torch.empty(shape, dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev)
+    ob = _lib.Outputs()
+    for k in OUTPUT_NAMES:
+        setattr(ob, k, res[k].data_ptr() if k in res else None)
+    arr = (_lib.Actor * max(len(actors), 1))()
+    for i, (sc, R, t) in enumerate(actors):
+        arr[i].scene_id = sc.id
+        arr[i].R[:] = [float(x) for x in np.asarray(R, np.float32).reshape(9)]
+        arr[i].t[:] = [float(x) for x in np.asarray(t, np.float32).reshape(3)]
+    work, mode = _schedule_args(schedule, sen, rays, dev)
+    call("salf_render_composite", scene.ctx.handle, scene.id, len(actors), arr,
+         C.byref(sen) if sen is not None else None, C.byref(rays) if rays is not None else None,
+         C.byref(_opts(samples, t_min, background, work, mode)), C.byref(ob), _stream(dev))
+    return res
+
+
 def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_near: float = 0.0,
                t_far: float = math.inf):
     """Voxels hit by each ray, front to back: counts [n] and ids/t_in/t_out [n, max_hits]

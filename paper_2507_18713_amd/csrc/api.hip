@@ -542,6 +542,50 @@ salf_status salf_render_work_size(const salf_sensor* sensor, const salf_rays* ra
   return SALF_OK;
 }
 
+salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, int32_t n_actors,
+                                  const salf_actor* actors, const salf_sensor* sensor, const salf_rays* rays,
+                                  const salf_render_opts* opts, const salf_outputs* out, void* stream) {
+  static_assert(SALF_MAX_ACTORS == kMaxActors, "actor count");
+  CompositeParams cp;
+  memset(&cp, 0, sizeof(cp));
+  int field = 0;
+  salf_status st = prepare_render(ctx, static_scene_id, sensor, rays, opts, &cp.base, &field);
+  if (st) return st;
+  if (!out) return set_error(SALF_ERR_INVALID_ARG, "outputs is NULL");
+  if (n_actors < 0 || n_actors > SALF_MAX_ACTORS || (n_actors > 0 && !actors))
+    return set_error(SALF_ERR_INVALID_ARG, "n_actors %d outside [0, %d] or actors NULL", n_actors, SALF_MAX_ACTORS);
+  const bool act = cp.base.scene.act_geo != nullptr;
+  auto check = [&](const SceneView& v, int fld) -> salf_status {
+    if (fld != SALF_FIELD_CORNER) return set_error(SALF_ERR_UNSUPPORTED, "actors render corner-field scenes only");
+    if ((v.act_geo != nullptr) != act)
+      return set_error(SALF_ERR_INVALID_ARG, "all scenes must be pre-activated, or none");
+    if (out->rgb && !v.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
+    if (out->intensity && !v.inten)
+      return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
+    return SALF_OK;
+  };
+  if ((st = check(cp.base.scene, field))) return st;
+  cp.n_actors = n_actors;
+  for (int a = 0; a < n_actors; ++a) {
+    Scene sc;
+    if ((st = scene_snapshot(ctx, actors[a].scene_id, &sc))) return st;
+    if ((st = check(sc.view, sc.desc.field))) return st;
+    for (int k = 0; k < 9; ++k)
+      if (!isfinite(actors[a].R[k])) return set_error(SALF_ERR_INVALID_ARG, "actor %d pose is not finite", a);
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(actors[a].t[k])) return set_error(SALF_ERR_INVALID_ARG, "actor %d pose is not finite", a);
+    cp.actor[a].view = sc.view;
+    memcpy(cp.actor[a].R, actors[a].R, sizeof(cp.actor[a].R));
+    memcpy(cp.actor[a].t, actors[a].t, sizeof(cp.actor[a].t));
+  }
+  cp.base.out = *out;
+  DeviceGuard g(ctx->device);
+  if (opts->schedule == SALF_SCHEDULE_BUILD &&
+      (st = check_hip(launch_tile_schedule(cp.base, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
+    return st;
+  return check_hip(launch_composite(cp, act, (hipStream_t)stream), "composite launch");
+}
+
 salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
                             int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream) {
   Scene sc;

@@ -106,6 +106,23 @@ inline void set_tiling(RenderParams* p, int sensor_model) {
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream);
 
+// A static scene (base.scene) with up to kMaxActors actors, each a scene placed by a rigid pose:
+// a world point p is the actor point R^T (p - t) (R row-major).
+constexpr int kMaxActors = 7;
+struct ActorPose {
+  SceneView view;
+  float R[9];
+  float t[3];
+};
+struct CompositeParams {
+  RenderParams base;
+  int32_t n_actors;
+  int32_t pad;
+  ActorPose actor[kMaxActors];
+};
+// Corner-field scenes, all with stored activated values (activated) or none.
+hipError_t launch_composite(const CompositeParams& cp, bool activated, hipStream_t stream);
+
 // One request of a batched launch (sensor mode, corner field).  variant: bit 0 colour, bit 1
 // intensity, bit 2 pre-activated corner values.
 struct BatchItem {

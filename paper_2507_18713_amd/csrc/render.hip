@@ -226,6 +226,114 @@ __global__ __launch_bounds__(kThreads) SALF_RENDER_OCCUPANCY void render_kernel(
   render_wave<FIELD, RGB, INT>(p, scheduled_tile(p, w), stk + threadIdx.x);
 }
 
+// ---- a static scene with dynamic actors (merged traversal)
+// The ray in an actor's frame: R^T (o - t), R^T d, each operation rounded in this order.
+__device__ __forceinline__ void actor_ray(const ActorPose& a, const float o[3], const float d[3], float oa[3],
+                                          float da[3]) {
+  const float p[3] = {o[0] - a.t[0], o[1] - a.t[1], o[2] - a.t[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    oa[i] = (a.R[i] * p[0] + a.R[3 + i] * p[1]) + a.R[6 + i] * p[2];
+    da[i] = (a.R[i] * d[0] + a.R[3 + i] * d[1]) + a.R[6 + i] * d[2];
+  }
+}
+
+// Each lane finds the actor boxes its ray meets, then walks the static scene up to the next box,
+// the actor inside it (in its frame), and so on, compositing every hit in that order; shading and
+// compositing are those of render_wave.
+template <int FIELD, bool RGB, bool INT>
+__global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  const RenderParams& p = cp.base;
+  const int64_t wave = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  int64_t ray;
+  float dir[3];
+  RayFrame f;
+  if (!lane_ray(p, scheduled_tile(p, wave), threadIdx.x & 63, ray, dir, f)) return;
+  const float sh[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // (corner field: no view-dependent term)
+  float a_in[kMaxActors], a_out[kMaxActors];
+#pragma unroll
+  for (int a = 0; a < kMaxActors; ++a) {
+    a_in[a] = INFINITY;
+    a_out[a] = -INFINITY;
+    if (a < cp.n_actors && f.valid) {
+      float oa[3], da[3];
+      actor_ray(cp.actor[a], f.o, f.d, oa, da);
+      const RayFrame fa = make_frame(cp.actor[a].view, oa, da, f.t_near, f.t_far);
+      const int K = cp.actor[a].view.K;
+      const int32_t glo[3] = {0, 0, 0};
+      const int32_t ghi[3] = {cp.actor[a].view.dims[0] << K, cp.actor[a].view.dims[1] << K,
+                              cp.actor[a].view.dims[2] << K};
+      float ti, to;
+      if (fa.valid && box_interval(fa, glo, ghi, ti, to) && ti < to) {
+        a_in[a] = ti;
+        a_out[a] = to;
+      }
+    }
+  }
+  Accum acc;
+  acc.T = 1.0f;
+  acc.C[0] = acc.C[1] = acc.C[2] = 0.0f;
+  acc.D = acc.I = 0.0f;
+  acc.n = 0;
+  const int S = p.S;
+  const double rS = 1.0 / S;
+  const float t_min = p.t_min;
+  bool alive = f.valid;
+  auto walk = [&](const SceneView& sv, const RayFrame& fr) {
+    traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+      alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
+      return alive;
+    });
+  };
+  float cur = f.t_near;
+  uint32_t done = 0;
+  for (int piece = 0; piece <= kMaxActors && alive; ++piece) {
+    // the next actor box along the ray (smallest entry, ties by index)
+    int nxt = -1;
+    float nin = INFINITY, nout = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < kMaxActors; ++a) {
+      if (!((done >> a) & 1u) && a_in[a] < nin) {
+        nin = a_in[a];
+        nout = a_out[a];
+        nxt = a;
+      }
+    }
+    const float s_end = nxt >= 0 ? nin : f.t_far;
+    if (cur < s_end) {
+      RayFrame fs = f;
+      fs.t_near = cur;
+      fs.t_far = s_end;
+      walk(p.scene, fs);
+    }
+    if (nxt < 0 || !alive) break;
+    done |= 1u << nxt;
+    SceneView av = cp.actor[0].view;
+    float oa[3], da[3];
+    actor_ray(cp.actor[0], f.o, f.d, oa, da);
+#pragma unroll
+    for (int a = 1; a < kMaxActors; ++a) {
+      if (a == nxt) {
+        av = cp.actor[a].view;
+        actor_ray(cp.actor[a], f.o, f.d, oa, da);
+      }
+    }
+    walk(av, make_frame(av, oa, da, nin, nout));
+    cur = fmaxf(cur, nout);
+  }
+  const salf_outputs& out = p.out;
+  if (out.rgb) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = fmaf(acc.T, p.bg[ch], acc.C[ch]);
+  }
+  if (out.depth) out.depth[ray] = acc.D;
+  if (out.opacity) out.opacity[ray] = 1.0f - acc.T;
+  if (out.intensity) out.intensity[ray] = acc.I;
+  if (out.t_end) out.t_end[ray] = acc.T;
+  if (out.n_hits) out.n_hits[ray] = acc.n;
+}
+
 // Request of global tile `tile` in a batch (items sorted by tile_begin, the first at 0).
 __device__ __forceinline__ int find_item(const BatchItem* items, int32_t n_items, int64_t tile) {
   int lo = 0, hi = n_items - 1;
@@ -752,6 +860,27 @@ hipError_t launch_batch_schedule(const BatchItem* d_items, int32_t n_items, int6
   RenderParams none;
   memset(&none, 0, sizeof(none));
   return schedule_tiles(none, d_items, n_items, n_tiles, kBatchScheduleTiles, work, stream);
+}
+
+hipError_t launch_composite(const CompositeParams& cp, bool activated, hipStream_t stream) {
+  const RenderParams& p = cp.base;
+  const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;
+  if (threads <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
+  const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
+  constexpr int A = kFieldCornerActivated, C = SALF_FIELD_CORNER;
+  if (activated) {
+    if (rgb && in) composite_kernel<A, true, true><<<blocks, kThreads, 0, stream>>>(cp);
+    else if (rgb) composite_kernel<A, true, false><<<blocks, kThreads, 0, stream>>>(cp);
+    else if (in) composite_kernel<A, false, true><<<blocks, kThreads, 0, stream>>>(cp);
+    else composite_kernel<A, false, false><<<blocks, kThreads, 0, stream>>>(cp);
+  } else {
+    if (rgb && in) composite_kernel<C, true, true><<<blocks, kThreads, 0, stream>>>(cp);
+    else if (rgb) composite_kernel<C, true, false><<<blocks, kThreads, 0, stream>>>(cp);
+    else if (in) composite_kernel<C, false, true><<<blocks, kThreads, 0, stream>>>(cp);
+    else composite_kernel<C, false, false><<<blocks, kThreads, 0, stream>>>(cp);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_render(const RenderParams& p, int field, hipStream_t stream) {
