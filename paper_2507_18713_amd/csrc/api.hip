@@ -583,6 +583,8 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
   if (opts->schedule == SALF_SCHEDULE_BUILD &&
       (st = check_hip(launch_tile_schedule(cp.base, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
     return st;
+  if (n_actors == 0)  // the same bits as the actor kernel, from the plain render kernel
+    return check_hip(launch_render(cp.base, field, (hipStream_t)stream), "render launch");
   return check_hip(launch_composite(cp, act, (hipStream_t)stream), "composite launch");
 }
 

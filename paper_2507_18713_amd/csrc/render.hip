@@ -309,17 +309,15 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
     }
     if (nxt < 0 || !alive) break;
     done |= 1u << nxt;
-    SceneView av = cp.actor[0].view;
-    float oa[3], da[3];
-    actor_ray(cp.actor[0], f.o, f.d, oa, da);
-#pragma unroll
-    for (int a = 1; a < kMaxActors; ++a) {
-      if (a == nxt) {
-        av = cp.actor[a].view;
-        actor_ray(cp.actor[a], f.o, f.d, oa, da);
-      }
+    // the lanes whose next box is actor a walk it, a running over the actors in step across the
+    // wave, so that each actor's scene stays uniform (scalar registers)
+#pragma unroll 1
+    for (int a = 0; a < cp.n_actors; ++a) {
+      if (a != nxt) continue;
+      float oa[3], da[3];
+      actor_ray(cp.actor[a], f.o, f.d, oa, da);
+      walk(cp.actor[a].view, make_frame(cp.actor[a].view, oa, da, nin, nout));
     }
-    walk(av, make_frame(av, oa, da, nin, nout));
     cur = fmaxf(cur, nout);
   }
   const salf_outputs& out = p.out;

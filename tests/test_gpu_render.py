@@ -532,8 +532,9 @@ def test_composite_render_matches_oracle(salf):
                                 background=opts.background, outputs=outs)
     ro, rd = rays["o"].cpu().numpy(), rays["d"].cpu().numpy()
     check_outputs(got, oracle.composite_rays(ps, aps, ro, rd, opts), keys=outs)
-    # without actors it is the plain render, bit for bit
+    # an actor no ray meets leaves the plain render, bit for bit (the actor kernel's static walk)
     plain = salf.render(sc, o=to_dev(o), d=to_dev(d), background=opts.background, outputs=outs)
-    none = salf.render_composite(sc, [], o=to_dev(o), d=to_dev(d), background=opts.background, outputs=outs)
+    far = salf.render_composite(sc, [(acts[0], np.eye(3, dtype=np.float32), np.array([500.0, 500.0, 500.0]))],
+                                o=to_dev(o), d=to_dev(d), background=opts.background, outputs=outs)
     for k in outs:
-        assert torch.equal(plain[k], none[k]), k
+        assert torch.equal(plain[k], far[k]), k
