@@ -566,6 +566,7 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
   };
   if ((st = check(cp.base.scene, field))) return st;
   cp.n_actors = n_actors;
+  cp.slot[0].view = cp.base.scene;
   for (int a = 0; a < n_actors; ++a) {
     Scene sc;
     if ((st = scene_snapshot(ctx, actors[a].scene_id, &sc))) return st;
@@ -574,9 +575,10 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
       if (!isfinite(actors[a].R[k])) return set_error(SALF_ERR_INVALID_ARG, "actor %d pose is not finite", a);
     for (int k = 0; k < 3; ++k)
       if (!isfinite(actors[a].t[k])) return set_error(SALF_ERR_INVALID_ARG, "actor %d pose is not finite", a);
-    cp.actor[a].view = sc.view;
-    memcpy(cp.actor[a].R, actors[a].R, sizeof(cp.actor[a].R));
-    memcpy(cp.actor[a].t, actors[a].t, sizeof(cp.actor[a].t));
+    ActorPose& sa = cp.slot[1 + a];
+    sa.view = sc.view;
+    memcpy(sa.R, actors[a].R, sizeof(sa.R));
+    memcpy(sa.t, actors[a].t, sizeof(sa.t));
   }
   cp.base.out = *out;
   DeviceGuard g(ctx->device);

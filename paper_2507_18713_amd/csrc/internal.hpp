@@ -118,7 +118,9 @@ struct CompositeParams {
   RenderParams base;
   int32_t n_actors;
   int32_t pad;
-  ActorPose actor[kMaxActors];
+  // slot[0]: the static scene, base.scene again (pose unused); slot[1 + a]: actor a.  One array, so
+  // that a kernel indexes every walked scene the same way.
+  ActorPose slot[kMaxActors + 1];
 };
 // Corner-field scenes, all with stored activated values (activated) or none.
 hipError_t launch_composite(const CompositeParams& cp, bool activated, hipStream_t stream);

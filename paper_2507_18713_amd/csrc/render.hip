@@ -251,23 +251,26 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
   RayFrame f;
   if (!lane_ray(p, scheduled_tile(p, wave), threadIdx.x & 63, ray, dir, f)) return;
   const float sh[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // (corner field: no view-dependent term)
-  float a_in[kMaxActors], a_out[kMaxActors];
+  // each lane's actor-box intervals, kept in LDS rather than registers (read once per piece)
+  __shared__ float a_in[kMaxActors][kThreads], a_out[kMaxActors][kThreads];
+  const int lt = threadIdx.x;
 #pragma unroll
   for (int a = 0; a < kMaxActors; ++a) {
-    a_in[a] = INFINITY;
-    a_out[a] = -INFINITY;
+    a_in[a][lt] = INFINITY;
+    a_out[a][lt] = -INFINITY;
     if (a < cp.n_actors && f.valid) {
+      const ActorPose& sa = cp.slot[1 + a];
       float oa[3], da[3];
-      actor_ray(cp.actor[a], f.o, f.d, oa, da);
-      const RayFrame fa = make_frame(cp.actor[a].view, oa, da, f.t_near, f.t_far);
-      const int K = cp.actor[a].view.K;
+      actor_ray(sa, f.o, f.d, oa, da);
+      const RayFrame fa = make_frame(sa.view, oa, da, f.t_near, f.t_far);
+      const int K = sa.view.K;
       const int32_t glo[3] = {0, 0, 0};
-      const int32_t ghi[3] = {cp.actor[a].view.dims[0] << K, cp.actor[a].view.dims[1] << K,
-                              cp.actor[a].view.dims[2] << K};
+      const int32_t ghi[3] = {sa.view.dims[0] << K, sa.view.dims[1] << K,
+                              sa.view.dims[2] << K};
       float ti, to;
       if (fa.valid && box_interval(fa, glo, ghi, ti, to) && ti < to) {
-        a_in[a] = ti;
-        a_out[a] = to;
+        a_in[a][lt] = ti;
+        a_out[a][lt] = to;
       }
     }
   }
@@ -280,45 +283,80 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
   const double rS = 1.0 / S;
   const float t_min = p.t_min;
   bool alive = f.valid;
-  auto walk = [&](const SceneView& sv, const RayFrame& fr) {
-    traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
-      alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
-      return alive;
-    });
-  };
+  // Pieces of the ray, front to back: the static scene from cur up to the next actor box, then that
+  // actor inside its box.  Each round every live lane picks its next piece; the wave then runs
+  // over the scene slots (static, actor 0, 1, ...) in step, the lanes whose piece is in slot k
+  // walking it, so that the walked scene is uniform and one walk serves every slot.
+  __shared__ float ray_o[3][kThreads], ray_d[3][kThreads], ray_tf[kThreads];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ray_o[a][lt] = f.o[a];
+    ray_d[a][lt] = f.d[a];
+  }
+  ray_tf[lt] = f.t_far;
   float cur = f.t_near;
   uint32_t done = 0;
-  for (int piece = 0; piece <= kMaxActors && alive; ++piece) {
+  bool ray_done = !alive;
+  for (int round = 0; round <= 2 * kMaxActors + 1 && !ray_done; ++round) {
     // the next actor box along the ray (smallest entry, ties by index)
     int nxt = -1;
     float nin = INFINITY, nout = -INFINITY;
 #pragma unroll
     for (int a = 0; a < kMaxActors; ++a) {
-      if (!((done >> a) & 1u) && a_in[a] < nin) {
-        nin = a_in[a];
-        nout = a_out[a];
+      const float ti = a_in[a][lt];
+      if (!((done >> a) & 1u) && ti < nin) {
+        nin = ti;
+        nout = a_out[a][lt];
         nxt = a;
       }
     }
-    const float s_end = nxt >= 0 ? nin : f.t_far;
+    // this round's piece: the static scene up to the next box if any is left, else the actor
+    const float s_end = nxt >= 0 ? nin : ray_tf[lt];
+    int slot;
+    float t0, t1;
     if (cur < s_end) {
-      RayFrame fs = f;
-      fs.t_near = cur;
-      fs.t_far = s_end;
-      walk(p.scene, fs);
+      slot = 0;
+      t0 = cur;
+      t1 = s_end;
+      cur = s_end;
+    } else if (nxt >= 0) {
+      slot = 1 + nxt;
+      t0 = nin;
+      t1 = nout;
+      done |= 1u << nxt;
+      cur = fmaxf(cur, nout);
+    } else {
+      ray_done = true;
+      continue;
     }
-    if (nxt < 0 || !alive) break;
-    done |= 1u << nxt;
-    // the lanes whose next box is actor a walk it, a running over the actors in step across the
-    // wave, so that each actor's scene stays uniform (scalar registers)
 #pragma unroll 1
-    for (int a = 0; a < cp.n_actors; ++a) {
-      if (a != nxt) continue;
-      float oa[3], da[3];
-      actor_ray(cp.actor[a], f.o, f.d, oa, da);
-      walk(cp.actor[a].view, make_frame(cp.actor[a].view, oa, da, nin, nout));
+    for (int k = 0; k <= cp.n_actors; ++k) {
+      if (k != slot) continue;
+      const SceneView& sv = cp.slot[k].view;
+      // the frame is rebuilt per piece (the static one as the lane built it, make_frame being a
+      // function of its arguments), so that only the ray itself stays live across pieces
+      float o[3], d[3], oa[3], da[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        o[a] = ray_o[a][lt];
+        d[a] = ray_d[a][lt];
+      }
+      if (k == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          oa[a] = o[a];
+          da[a] = d[a];
+        }
+      } else {
+        actor_ray(cp.slot[k], o, d, oa, da);
+      }
+      const RayFrame fr = make_frame(sv, oa, da, t0, t1);
+      traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+        alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
+        return alive;
+      });
     }
-    cur = fmaxf(cur, nout);
+    if (!alive) ray_done = true;
   }
   const salf_outputs& out = p.out;
   if (out.rgb) {
