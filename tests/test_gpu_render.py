@@ -538,3 +538,59 @@ def test_composite_render_matches_oracle(salf):
                                 o=to_dev(o), d=to_dev(d), background=opts.background, outputs=outs)
     for k in outs:
         assert torch.equal(plain[k], far[k]), k
+
+
+def test_composite_edge_cases_match_oracle(salf):
+    """The maximum of seven actors, two of them with overlapping boxes (both sides then walk each
+    box whole, in order of entry), rays that start inside an actor box or run along an axis, and a
+    spinning LiDAR among the actors: hits exactly, outputs within the render tolerance; the fused
+    sensor path equals explicit rays bit for bit."""
+    static = synth.random_scene(111, root_dims=(4, 4, 2), max_level=2, root_size=1.0, origin=(-2.0, -2.0, -1.0))
+    lvl = static.voxels[:, 0].astype(np.int64)
+    cx = static.voxels[:, 1].astype(np.int64) >> lvl
+    static = static.subset(cx < 2)          # the background keeps x < 0
+    centres = [(2.0, -3.0, 0.0), (3.5, -1.5, 0.0), (3.5, 1.5, 0.0), (2.0, 3.0, 0.0), (-2.0, 3.5, 0.0),
+               (-2.0, -3.5, 0.0), (-1.7, -3.3, 0.2)]      # the last two boxes overlap
+    actors, poses = [], []
+    for a, c in enumerate(centres):
+        data = synth.random_scene(120 + a, root_dims=(2, 2, 2), max_level=2, root_size=0.4, origin=(0.0, 0.0, 0.0))
+        R = _rotation(130 + a)
+        t = (np.array(c) - R.astype(np.float64) @ np.array([0.4, 0.4, 0.4])).astype(np.float32)
+        actors.append(data)
+        poses.append((R, t))
+    assert len(actors) == 7                 # the most one call takes
+    opts = RenderOpts(background=(0.3, 0.1, 0.2))
+    sc = salf.Scene.from_data(static, device=dev(), preactivate=True)
+    acts = [salf.Scene.from_data(a, device=dev(), preactivate=True) for a in actors]
+    items = [(s, R, t) for s, (R, t) in zip(acts, poses)]
+    ps = oracle.prepare(static)
+    aps = [(oracle.prepare(a), R, t) for a, (R, t) in zip(actors, poses)]
+    rng = np.random.default_rng(141)
+    # rays from inside each box, rays along the axes through the actor ring, random rays
+    o_in = np.repeat(np.array(centres, np.float32), 40, axis=0) + rng.uniform(-0.2, 0.2, (280, 3)).astype(F32)
+    d_in = rng.normal(size=(280, 3)).astype(F32)
+    o_ax = np.zeros((6, 3), F32)
+    d_ax = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], F32)
+    o_ax[:, 2] = 0.05
+    o_r, d_r = synth.random_rays(142, 600, np.array([-5.0, -5.0, -2.0]), np.array([5.0, 5.0, 2.0]), inside_frac=0.3)
+    o = np.concatenate([o_in, o_ax, o_r.astype(F32)])
+    d = np.concatenate([d_in, d_ax, d_r.astype(F32)])
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    got = salf.render_composite(sc, items, o=to_dev(o), d=to_dev(d), background=opts.background, outputs=outs)
+    ref = oracle.composite_rays(ps, aps, o, d, opts)
+    assert int((ref["n_hits"][:280] > 0).sum()) > 150
+    check_outputs(got, ref, keys=outs)
+    # a spinning LiDAR at the middle of the ring (with ego motion), fused against explicit rays
+    lid = synth.lidar_spinning(16, 128, -20, 10, np.eye(3), (0.8, 0.1, 0.1), 0.1, v=(5, 0, 0))
+    fused = salf.render_composite(sc, items, sensor=lid, background=opts.background, outputs=outs)
+    r = salf.generate_rays(lid, device=dev())
+    expl = salf.render_composite(sc, items, o=r["o"], d=r["d"], background=opts.background, outputs=outs,
+                                 image_width=lid["width"])
+    valid = r["valid"].bool()
+    for k in outs:
+        assert torch.equal(fused[k][valid], expl[k][valid]), k
+    ro, rd = r["o"].cpu().numpy(), r["d"].cpu().numpy()
+    vi = np.nonzero(valid.cpu().numpy())[0]
+    ref = oracle.composite_rays(ps, aps, ro[vi], rd[vi], opts)
+    assert int((ref["n_hits"] > 0).sum()) > 200
+    check_outputs(fused, ref, idx=vi, keys=outs)
