@@ -412,6 +412,38 @@ def actors_pass(salf, torch, dev, data, scene, cam, opts, steps, n_actors=7):
     return rec
 
 
+def batched_pass(salf, torch, dev, scene, cam, lid, steps):
+    """The step's camera frame and LiDAR sweep submitted to the server each tick, so that both
+    sensors' tiles go out in one cost-ordered batched launch, two ticks in flight (the server's
+    host round trip between launches hidden).  Wall time per tick over `steps` ticks, after 3."""
+    import time as _t
+    srv = salf.Server(1 << 30, device=dev, max_batch=2, max_inflight=2)
+    n = cam["width"] * cam["height"] + lid["width"] * lid["height"]
+
+    def tick():
+        return (srv.submit(scene, cam, outputs=("rgb", "depth", "opacity")),
+                srv.submit(scene, lid, outputs=("depth", "intensity", "opacity")))
+
+    def drain(ts):
+        for a, b in ts:
+            srv.wait(a)
+            srv.wait(b)
+            srv.release(a)
+            srv.release(b)
+
+    drain([tick() for _ in range(3)])
+    torch.cuda.synchronize()
+    launches0 = srv.stats()["launches"]
+    t0 = _t.perf_counter()
+    drain([tick() for _ in range(steps)])
+    torch.cuda.synchronize()
+    dt = (_t.perf_counter() - t0) / steps
+    launches = srv.stats()["launches"] - launches0
+    srv.close()
+    return {"ms_per_tick": round(dt * 1e3, 4), "mrays_s": round(n / dt / 1e6, 1), "ticks": steps,
+            "launches": launches}
+
+
 def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, seed=6, field="paper"):
     """Forward and backward of the same batch on the driving scene's voxels with the paper's field
     (Eq. 1-2): seeded parameters, density slopes N(0, 0.5^2) and offset N(0, 1) - 1, colour and
@@ -616,6 +648,7 @@ def main():
     torch.cuda.synchronize()
     cam_raw_ms = e0.elapsed_time(e1) / args.steps
     actors_rec = actors_pass(salf, torch, dev, data, scene, cam, opts, args.steps)
+    batched_rec = None if args.no_serving else batched_pass(salf, torch, dev, scene, cam, lid, args.steps)
 
     cam_bytes = hits_cam * CAM_HIT_BYTES + n_cam * CAM_RAY_BYTES
     lid_bytes = hits_lid * LID_HIT_BYTES + n_lid * LID_RAY_BYTES
@@ -659,6 +692,7 @@ def main():
         "step": "camera frame and LiDAR sweep rendered concurrently on two streams",
         "scene_build_ms": round(build_ms, 3),
         "actors": actors_rec,
+        "batched_step": batched_rec,
         "dense_index_bytes": int(scene.index.numel()) if scene.index is not None else 0,
         "scene_generate_s": round(t_gen, 2),
         "kernel_source_hash": kernel_source_hash(),
