@@ -775,3 +775,156 @@ def test_axis_parallel_rays_on_faces_use_half_open_slabs():
     # on the grid's top face the ray is outside every cell
     ids, _, _ = oracle.hit_list(ps, np.array([-2.0, 4.0, 1.0], F32), np.array([1.0, 0.0, 0.0], F32))
     assert ids.size == 0
+
+
+# ---------------------------------------------------------------- actors under rotated poses
+_RZ90 = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], np.float64)    # +90 deg about z
+_RX90 = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], np.float64)    # +90 deg about x
+
+
+def _slab_as_actor(sc, cell_lo, cell_hi, R):
+    """Cut the voxels of the root-cell box [cell_lo, cell_hi) out of `sc` into an actor scene in a
+    canonical frame rotated by the signed permutation R (a world point p is the actor point
+    R^T (p - t)).  The actor's grid has its min corner at its origin 0; t is the translation that
+    puts it back over the box.  Voxel coordinates and the order of the 8 corner values are mapped
+    by hand: actor axis j runs along world axis i where R[i, j] != 0, reversed when it is -1.
+    Returns (static scene, actor scene, t)."""
+    K, s0 = sc.max_level, float(sc.root_size)
+    sK = s0 / (1 << K)
+    lvl = sc.voxels[:, 0].astype(np.int64)
+    cell = sc.voxels[:, 1:4].astype(np.int64) >> lvl[:, None]
+    inside = np.all((cell >= cell_lo) & (cell < cell_hi), axis=1)
+    static, act = sc.subset(~inside), sc.subset(inside)
+    box_lo = np.asarray(sc.origin, float) + np.asarray(cell_lo, float) * s0
+    box_hi = np.asarray(sc.origin, float) + np.asarray(cell_hi, float) * s0
+    corners = np.array([[(box_lo, box_hi)[(c >> a) & 1][a] for a in range(3)] for c in range(8)])
+    a_min = (corners @ R).min(axis=0)          # R^T p for each corner, row-wise
+    t = R @ a_min
+    dims = np.rint(np.abs(R.T) @ (np.asarray(cell_hi) - np.asarray(cell_lo))).astype(np.int64)
+    # voxels: world finest-unit box -> actor metres -> actor finest units
+    a_lvl = act.voxels[:, 0].astype(np.int64)
+    n = np.left_shift(1, K - a_lvl)
+    lo_w = np.asarray(sc.origin, float) + act.voxels[:, 1:4].astype(np.int64) * n[:, None] * sK
+    hi_w = lo_w + n[:, None] * sK
+    a_lo = np.minimum(lo_w @ R, hi_w @ R) - a_min
+    lo_f = a_lo / sK
+    assert np.allclose(lo_f, np.rint(lo_f), atol=1e-6)
+    coords = np.rint(lo_f).astype(np.int64) // n[:, None]
+    vox = np.concatenate([a_lvl[:, None], coords], 1).astype(np.int32)
+    # corner c' of the actor voxel (bits b'_j) sits at world corner bits b_i = b'_j or 1 - b'_j
+    perm = np.empty(8, np.int64)
+    for cp in range(8):
+        c = 0
+        for i in range(3):
+            j = int(np.nonzero(R[i])[0][0])
+            bj = (cp >> j) & 1
+            c |= (bj if R[i, j] > 0 else 1 - bj) << i
+        perm[cp] = c
+    actor = synth.SceneData(origin=np.zeros(3), root_size=s0, root_dims=dims, max_level=K, voxels=vox,
+                            z_geo=act.z_geo[:, perm].copy(), z_rgb=act.z_rgb[:, :, perm].copy(),
+                            z_int=None if act.z_int is None else act.z_int[:, perm].copy(), name="actor")
+    return static, actor, t
+
+
+@pytest.mark.parametrize("rot", ["z90", "x90", "z90x90"])
+def test_composite_rotated_actor_equals_the_merged_scene(rot):
+    """A slab of root cells moved into an actor whose canonical frame is rotated by an exact 90 deg
+    turn (about z, about x, and both) and translated by whole cells renders like the original
+    scene.  A transposed R, or t applied after the rotation, sends the actor's rays elsewhere."""
+    R = {"z90": _RZ90, "x90": _RX90, "z90x90": _RZ90 @ _RX90}[rot]
+    sc = synth.random_scene(75, root_dims=(6, 4, 3), max_level=2, fill=0.7, origin=(-3.0, -2.0, -1.5))
+    static, actor, t = _slab_as_actor(sc, (2, 1, 0), (4, 4, 3), R)
+    assert static.n > 20 and actor.n > 20
+    o, d = synth.random_rays(76, 400, sc.origin, sc.origin + sc.root_dims * sc.root_size)
+    opts = RenderOpts(background=(0.1, 0.2, 0.3))
+    got = oracle.composite_rays(oracle.prepare(static), [(oracle.prepare(actor), R, t)], o, d, opts)
+    ref = oracle.render_rays(oracle.prepare(sc), o, d, opts)
+    # up to the rounding of the actor frame's own origin, the hit lists are the same
+    assert np.mean(got["n_hits"] != ref["n_hits"]) <= 0.01
+    same = got["n_hits"] == ref["n_hits"]
+    for k in ("rgb", "depth", "opacity", "intensity"):
+        assert np.max(np.abs(got[k][same] - ref[k][same])) <= 1e-5, k
+    # the actor's voxels are really met: the rays that cross the slab see them
+    assert int(ref["n_hits"].sum()) > 400
+    # the transposed rotation is a different pose: it does not reproduce the scene
+    bad = oracle.composite_rays(oracle.prepare(static), [(oracle.prepare(actor), R.T, t)], o, d, opts)
+    assert np.mean(bad["n_hits"] != ref["n_hits"]) > 0.05
+
+
+def _segments_closed_form(segs, S, bg):
+    """Outputs of constant-field segments (sigma, rgb, intensity, t_in, t_out) composited front to
+    back with S midpoint samples each (Eq. 3-4 written out for constant density)."""
+    T, C, D, I = 1.0, np.zeros(3), 0.0, 0.0
+    for sig, col, inten, t0, t1 in segs:
+        L = t1 - t0
+        tau = sig * L / S
+        for k in range(S):
+            w = T * math.exp(-k * tau) * (1.0 - math.exp(-tau))
+            C += w * np.asarray(col)
+            D += w * (t0 + (k + 0.5) * L / S)
+            I += w * inten
+        T *= math.exp(-sig * L)
+    return C + T * np.asarray(bg), D, 1.0 - T, I
+
+
+@pytest.mark.parametrize("S", [1, 3])
+def test_composite_overlapping_boxes_hand_derived(S):
+    """Two actors whose boxes overlap along a ray: each box is walked whole in order of entry, and
+    the static scene resumes after the furthest exit, so a static voxel inside the boxes' span is
+    skipped.  Static cells 0, 2, 4 of a 6 x 1 x 1 grid of 1 m cells; actor A is one 2 m voxel over
+    x in [1, 3], actor B (turned 90 deg about x) one over x in [2, 4]; the ray runs along +x from
+    x = -1.  Segments: static cell 0 on t in [1, 2], A on [2, 4], B on [3, 5], static cell 4 on
+    [5, 6]."""
+    zs = {0: -1.0, 2: 2.0, 4: 0.5}
+    cols = {0: (0.25, -0.5, 1.0), 2: (1.5, 1.5, 1.5), 4: (-1.0, 0.75, 0.0)}
+    ints = {0: 0.5, 2: -2.0, 4: 1.25}
+    cells = sorted(zs)
+    static = synth.SceneData(origin=np.zeros(3), root_size=1.0, root_dims=np.array([6, 1, 1]), max_level=0,
+                             voxels=np.array([[0, c, 0, 0] for c in cells], np.int32),
+                             z_geo=np.array([[zs[c]] * 8 for c in cells], F32),
+                             z_rgb=np.array([np.repeat(np.array(cols[c])[:, None], 8, 1) for c in cells], F32),
+                             z_int=np.array([[ints[c]] * 8 for c in cells], F32))
+    a = synth.single_voxel_scene(np.full(8, 0.0), np.repeat(np.array([0.5, 0.0, -0.5])[:, None], 8, 1),
+                                 np.full(8, -0.25), root_size=2.0)
+    b = synth.single_voxel_scene(np.full(8, -0.5), np.repeat(np.array([-0.25, 1.0, 0.25])[:, None], 8, 1),
+                                 np.full(8, 0.75), root_size=2.0)
+    poses = [(np.eye(3), np.array([1.0, -0.5, -0.5])), (_RX90, np.array([2.0, 1.5, -0.5]))]
+    o = np.array([[-1.0, 0.5, 0.5]], F32)
+    d = np.array([[1.0, 0.0, 0.0]], F32)
+    bg = (0.1, 0.2, 0.3)
+    opts = RenderOpts(samples=S, t_min=0.0, background=bg)
+    got = oracle.composite_rays(oracle.prepare(static), [(oracle.prepare(a), *poses[0]), (oracle.prepare(b), *poses[1])],
+                                o, d, opts)
+    seg = [(_sp(zs[0]), [_sig(x) for x in cols[0]], _sig(ints[0]), 1.0, 2.0),
+           (_sp(0.0), [_sig(x) for x in (0.5, 0.0, -0.5)], _sig(-0.25), 2.0, 4.0),
+           (_sp(-0.5), [_sig(x) for x in (-0.25, 1.0, 0.25)], _sig(0.75), 3.0, 5.0),
+           (_sp(zs[4]), [_sig(x) for x in cols[4]], _sig(ints[4]), 5.0, 6.0)]
+    C, D, O, I = _segments_closed_form(seg, S, bg)
+    assert got["n_hits"][0] == 4
+    assert np.allclose(got["rgb"][0], C, atol=1e-12, rtol=0)
+    assert abs(got["depth"][0] - D) < 1e-12 and abs(got["opacity"][0] - O) < 1e-12
+    assert abs(got["intensity"][0] - I) < 1e-12
+
+
+# ---------------------------------------------------------------- paper-field intensity
+def test_paper_field_intensity_closed_forms():
+    """Eq. 1 density with zero slopes is constant, so O = 1 - exp(-sigma L); the intensity
+    sigmoid(w_I . [x, 1]) with zero slopes is sigmoid(b) everywhere, so I = sigmoid(b) O.  With
+    slopes along x and z only, a ray along +y at fixed local (x0, z0) sees the constant
+    sigmoid(w_x x0 + w_z z0 + b): this pins the slot and the sign of each slope."""
+    b_sig, b_int = -0.5, 0.75
+    for w, (x0, z0) in (((0.0, 0.0, 0.0), (0.25, -0.5)), ((1.5, 0.0, -2.0), (0.25, -0.5)),
+                        ((1.5, 0.0, -2.0), (-0.75, 0.5))):
+        zg = np.zeros(8)
+        zg[3] = b_sig
+        zi = np.zeros(8)
+        zi[:3], zi[3] = w, b_int
+        sc = synth.single_voxel_scene(zg, np.zeros((3, 8)), zi, root_size=2.0, origin=(-1.0, -1.0, -1.0))
+        ps = oracle.prepare(sc)
+        o = np.array([x0, -3.0, z0], F32)
+        d = np.array([0.0, 1.0, 0.0], F32)
+        for S in (1, 4):
+            out = oracle.render_ray(ps, o, d, RenderOpts(samples=S, field="paper", t_min=0.0))
+            O = 1.0 - math.exp(-math.exp(b_sig) * 2.0)
+            assert abs(out["opacity"] - O) < 1e-12
+            assert abs(out["intensity"] - _sig(w[0] * x0 + w[2] * z0 + b_int) * O) < 1e-12
