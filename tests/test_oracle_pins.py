@@ -928,3 +928,118 @@ def test_paper_field_intensity_closed_forms():
             O = 1.0 - math.exp(-math.exp(b_sig) * 2.0)
             assert abs(out["opacity"] - O) < 1e-12
             assert abs(out["intensity"] - _sig(w[0] * x0 + w[2] * z0 + b_int) * O) < 1e-12
+
+
+# ------------------------------------------------------------------ tile-based splatting (Sec. 3.2)
+def _raster_cameras(data):
+    """Pinholes around and inside an adaptive scene: outside looking in (ragged 40 x 30 image, 3 x 2
+    tiles), looking straight down, inside the grid, and with the eye exactly on root and mid planes."""
+    lo = np.asarray(data.origin, np.float64)
+    ext = np.asarray(data.root_dims, np.float64) * data.root_size
+    c = lo + ext / 2
+    s0 = data.root_size
+    eyes = [(c + np.array([1.3, -1.1, 0.7]) * ext.max(), c, 70.0),
+            (c + np.array([0.05, 0.02, 1.5]) * ext.max(), c, 60.0),
+            (lo + np.array([0.37, 0.41, 0.33]) * ext, c + np.array([0.2, 0.1, 0.05]) * ext, 100.0),
+            (lo + np.array([2.0, 1.5, 1.0]) * s0, c + np.array([0.3, 0.2, -0.1]) * ext, 90.0),
+            (lo + np.array([1.5, 2.25, 0.5]) * s0, lo + np.array([0.9, 0.2, 0.8]) * ext, 90.0)]
+    return [synth.pinhole(40, 30, fov, synth.look_at(e, t), e) for e, t, fov in eyes]
+
+
+@pytest.mark.parametrize("seed,K", [(301, 1), (302, 2), (303, 3)])
+def test_raster_octree_order_equals_ray_casting(seed, K):
+    """With the front-to-back octree key, splatting composites every pixel's hits in its ray's t_in
+    order, so each pixel equals the ray cast of its ray exactly (every output, float64 ==), for
+    cameras outside, above and inside the grid, eyes on grid planes, S = 1 and 4, with and without
+    early termination; every composited list is the prefix of the pixel ray's hit list."""
+    data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=K, fill=0.7)
+    ps = oracle.prepare(data)
+    for cam, (S, tmin, bg) in zip(_raster_cameras(data), [(4, 1e-6, (0.1, 0.2, 0.3)), (1, 0.0, (0, 0, 0)),
+                                                           (4, 1e-2, (0.5, 0.5, 0.5)), (1, 1e-6, (0, 0, 0)),
+                                                           (2, 1e-6, (0.2, 0.1, 0.0))]):
+        opts = RenderOpts(samples=S, t_min=tmin, background=bg)
+        out, comp = oracle.raster(ps, cam, opts)
+        o, d, _, _ = oracle.sensor_rays(cam)
+        o, d = o.astype(F32), d.astype(F32)
+        ref = oracle.render_rays(ps, o, d, opts)
+        for k in out:
+            assert np.array_equal(out[k], ref[k]), k
+        hit = 0
+        for r in range(o.shape[0]):
+            ids, _, _ = oracle.hit_list(ps, o[r], d[r])
+            n = int(ref["n_hits"][r])
+            assert np.array_equal(comp[r], ids[:n]), r
+            hit += n
+        assert hit > 200
+
+
+def test_raster_keys_increase_along_every_ray_and_centre_depth_does_not():
+    """The octree key strictly increases along the hit list of every pixel ray, whatever the eye's
+    position; the centre-depth key (the 3D Gaussian splatting order) inverts some neighbouring
+    hits, so splatting in that order differs from ray casting at some pixels."""
+    bad_centre = 0
+    for seed, K in ((311, 2), (312, 3)):
+        data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=K, fill=0.8)
+        ps = oracle.prepare(data)
+        for cam in _raster_cameras(data):
+            o, d, _, _ = oracle.sensor_rays(cam)
+            o, d = o.astype(F32), d.astype(F32)
+            kc = {}
+            for r in range(0, o.shape[0], 3):
+                ids, _, _ = oracle.hit_list(ps, o[r], d[r])
+                ko = [oracle.depth_key(ps, cam, int(v)) for v in ids]
+                assert all(a < b for a, b in zip(ko, ko[1:])), (seed, r)
+                for v in ids:
+                    if v not in kc:
+                        kc[v] = oracle.depth_key(ps, cam, int(v), kind="centre")
+                c = [kc[v] for v in ids]
+                bad_centre += sum(a > b for a, b in zip(c, c[1:]))
+    assert bad_centre > 0
+    data = synth.random_scene(312, root_dims=(5, 4, 3), max_level=3, fill=0.8)
+    ps = oracle.prepare(data)
+    cam = _raster_cameras(data)[2]
+    o, d, _, _ = oracle.sensor_rays(cam)
+    ref = oracle.render_rays(ps, o.astype(F32), d.astype(F32), RenderOpts(t_min=0.0))
+    out, _ = oracle.raster(ps, cam, RenderOpts(t_min=0.0), kind="centre")
+    differ = np.sum(np.abs(out["depth"] - ref["depth"]) > 1e-9)
+    assert differ > 0 and np.array_equal(out["t_end"] > 0, ref["t_end"] > 0)
+
+
+def test_raster_culling_and_footprints():
+    """Voxels wholly behind the camera are culled and no pixel ray hits them; a voxel reaching
+    across the camera plane covers every tile; every voxel a pixel ray hits is in the list of that
+    pixel's tile (and a one-voxel scene seen head-on covers exactly the tiles its image touches)."""
+    data = synth.random_scene(321, root_dims=(6, 4, 3), max_level=2, fill=0.8)
+    ps = oracle.prepare(data)
+    lo = np.asarray(data.origin, np.float64)
+    eye = lo + np.array([3.02, 2.01, 1.53]) * data.root_size       # inside the grid, looking +x
+    cam = synth.pinhole(48, 32, 90.0, synth.look_at(eye, eye + np.array([1.0, 0.0, 0.0])), eye)
+    fps = oracle.footprints(ps, cam)
+    o, d, _, _ = oracle.sensor_rays(cam)
+    o, d = o.astype(F32), d.astype(F32)
+    gs = ps.gs
+    xmax = ps.origin[0] + (ps.lo_i[:, 0] + ps.n_i) / gs
+    xmin = ps.origin[0] + ps.lo_i[:, 0] / gs
+    behind = xmax <= eye[0]
+    straddle = (xmin < eye[0]) & (xmax > eye[0])
+    assert behind.sum() > 10 and straddle.sum() > 0
+    for v in np.nonzero(behind)[0]:
+        assert fps[v] is None
+    for v in np.nonzero(straddle)[0]:
+        assert fps[v] == (0, 0, 2, 1)
+    lists = oracle.tile_lists(ps, cam)
+    for r in range(o.shape[0]):
+        ids, _, _ = oracle.hit_list(ps, o[r], d[r])
+        assert not np.any(behind[ids])
+        tile = lists.get(((r % 48) // 16, (r // 48) // 16), np.zeros(0, np.int64))
+        assert np.all(np.isin(ids, tile)), r
+    # one voxel filling the middle of a 64 x 64 view: its image spans pixels 16..47 (2 x 2 tiles)
+    one = synth.single_voxel_scene(np.zeros(8, F32), np.zeros((3, 8), F32), root_size=2.0, origin=(-1.0, -1.0, -1.0))
+    ps1 = oracle.prepare(one)
+    f = 32.0 / math.tan(math.radians(45.0))                         # 90 deg: fx = 32
+    eye = np.array([0.0, 0.0, -5.0])                                 # the near face at z = -1 is 4 m away
+    cam = synth.pinhole(64, 64, 90.0, synth.look_at(eye, (0.0, 0.0, 0.0), up=(0.0, -1.0, 0.0)), eye)
+    assert abs(cam["fx"] - f) < 1e-9
+    # near face corners project to 32 +- 32 * 1/4 = 24..40, far face (6 m) to 32 +- 32/6
+    assert oracle.footprints(ps1, cam, margin=0.0) == [(1, 1, 2, 2)]
+    assert oracle.footprints(ps1, cam, margin=9.0) == [(0, 0, 3, 3)]
