@@ -343,6 +343,23 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
                         const salf_rays* rays, const salf_render_opts* opts, const salf_outputs* out,
                         void* stream);
 
+/* Render without any caller memory for the tile schedule: as salf_render with
+ * opts->schedule = SALF_SCHEDULE_BUILD, except that the schedule is built in a fixed array the
+ * library holds on each device (SALF_STATIC_SCHEDULE_BYTES, allocated once per process when the
+ * library's code is loaded on that device, kept until the process ends).  For callers that cannot
+ * allocate device memory during rendering: code under stream capture, tight serving loops, hosts
+ * that forbid allocation.  The call allocates nothing (no hipMalloc, no library allocation);
+ * opts->schedule, d_work and work_bytes are ignored.  Every call on a device shares that device's
+ * array and overwrites it, so calls that overlap in time on one device (other streams, other
+ * threads, other contexts of the device) race and must be serialized by the caller.  Outputs are
+ * the same bits as salf_render's.  Errors: as salf_render, plus OUT_OF_MEMORY when the launch has
+ * more than SALF_STATIC_SCHEDULE_TILES tiles of 64 rays (the array holds no larger schedule). */
+#define SALF_STATIC_SCHEDULE_TILES (1 << 18)
+#define SALF_STATIC_SCHEDULE_BYTES (2 * SALF_STATIC_SCHEDULE_TILES * 4 + 2304)
+salf_status salf_render_static(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                               const salf_rays* rays, const salf_render_opts* opts, const salf_outputs* out,
+                               void* stream);
+
 /* ------------------------------------------------------------------ dynamic actors */
 /* An actor: a scene in its own canonical frame placed by a rigid pose, a world point p being the
  * actor point R^T (p - t) (R row-major, orthonormal). */

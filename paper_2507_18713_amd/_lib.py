@@ -106,6 +106,8 @@ SIGNATURES = {
                                        C.c_void_p, C.c_void_p]),
     "salf_render": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(RenderOpts),
                                 C.POINTER(Outputs), C.c_void_p]),
+    "salf_render_static": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
+                                       C.POINTER(RenderOpts), C.POINTER(Outputs), C.c_void_p]),
     "salf_render_work_size": (C.c_int32, [C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(C.c_size_t)]),
     "salf_render_schedule": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
                                          C.POINTER(RenderOpts), C.c_void_p]),

@@ -308,7 +308,9 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
     image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
     schedule: True builds a heaviest-tiles-first schedule in the call, a buffer from
-    render_schedule reuses one, False keeps tile order (the outputs are the same bits).
+    render_schedule reuses one, False keeps tile order, "static" builds it in the library's own
+    per-device array (salf_render_static: no schedule memory is allocated; calls on one device
+    must not overlap).  The outputs are the same bits in every case.
     Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
     n_hits int32 [n])."""
     dev = scene.device
@@ -331,6 +333,13 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     ob = _lib.Outputs()
     for k in OUTPUT_NAMES:
         setattr(ob, k, res[k].data_ptr() if k in res else None)
+    if isinstance(schedule, str):
+        if schedule != "static":
+            raise ValueError(f"unknown schedule {schedule!r}")
+        call("salf_render_static", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
+             C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(ob),
+             _stream(dev))
+        return res
     work, mode = _schedule_args(schedule, sen, rays, dev)
     call("salf_render", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
          C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work, mode)),

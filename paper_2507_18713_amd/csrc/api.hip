@@ -50,6 +50,12 @@ struct DeviceGuard {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// The tile-schedule array of salf_render_static: one copy per device, for the process's lifetime.
+// Host code never uses this name as an address (on the host it only stands for the symbol): the
+// device address is looked up once per context with hipGetSymbolAddress and kept in the context.
+static_assert(tile_work_bytes(SALF_STATIC_SCHEDULE_TILES) == SALF_STATIC_SCHEDULE_BYTES, "static schedule size");
+static __device__ __align__(256) uint8_t scratch[SALF_STATIC_SCHEDULE_BYTES];
+
 salf_status validate_desc(const salf_scene_desc* d) {
   if (!d) return set_error(SALF_ERR_INVALID_ARG, "scene desc is NULL");
   if (!(d->root_size > 0.0) || !isfinite(d->root_size))
@@ -255,9 +261,17 @@ salf_status salf_create(int32_t hip_device, salf_context** out) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
     return set_error(SALF_ERR_INVALID_ARG, "no HIP device %d (found %d)", hip_device, count);
+  void* sched = nullptr;
+  {
+    DeviceGuard g(hip_device);
+    if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", hip_device);
+    salf_status st = check_hip(hipGetSymbolAddress(&sched, HIP_SYMBOL(scratch)), "static schedule address");
+    if (st) return st;
+  }
   salf_context* c = new (std::nothrow) salf_context();
   if (!c) return set_error(SALF_ERR_OUT_OF_MEMORY, "host allocation failed");
   c->device = hip_device;
+  c->static_sched = sched;
   *out = c;
   return SALF_OK;
 }
@@ -517,6 +531,24 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
       (st = check_hip(launch_tile_schedule(p, opts->d_work, (hipStream_t)stream), "tile schedule launch")))
     return st;
   return check_hip(launch_render(p, field, (hipStream_t)stream), "render launch");
+}
+
+salf_status salf_render_static(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, const salf_rays* rays,
+                               const salf_render_opts* opts, const salf_outputs* out, void* stream) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  if (!opts) return set_error(SALF_ERR_INVALID_ARG, "render opts is NULL");
+  RenderParams lay;
+  memset(&lay, 0, sizeof(lay));
+  salf_status st = ray_layout(sensor, rays, &lay);
+  if (st) return st;
+  if (tile_count(lay) > SALF_STATIC_SCHEDULE_TILES)
+    return set_error(SALF_ERR_OUT_OF_MEMORY, "the launch has %lld tiles; the static schedule holds at most %d",
+                     (long long)tile_count(lay), SALF_STATIC_SCHEDULE_TILES);
+  salf_render_opts o = *opts;
+  o.schedule = SALF_SCHEDULE_BUILD;
+  o.d_work = ctx->static_sched;
+  o.work_bytes = SALF_STATIC_SCHEDULE_BYTES;
+  return salf_render(ctx, scene_id, sensor, rays, &o, out, stream);
 }
 
 salf_status salf_render_schedule(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,

@@ -88,9 +88,15 @@ __host__ __device__ inline int64_t tile_count(const RenderParams& p) {
   return p.tiled ? (int64_t)p.tiles_x * p.tiles_y : (p.n + 63) / 64;
 }
 
-// Bytes of the tile-schedule buffer for n_tiles tiles, and the schedule itself: cost estimates
-// and a heaviest-first order of p's tiles written to `work`, tagged with p's ray layout.
-size_t tile_work_bytes(int64_t n_tiles);
+// Logarithmic cost buckets of the tile schedule's counting sort.
+constexpr int kCostBuckets = 256;
+
+// Bytes of the tile-schedule buffer for n_tiles tiles (header, cost keys, order, histogram and
+// cursors), and the schedule itself: cost estimates and a heaviest-first order of p's tiles
+// written to `work`, tagged with p's ray layout.
+constexpr size_t tile_work_bytes(int64_t n_tiles) {
+  return kSchedHeader * 4 + 2 * ((((size_t)n_tiles * 4) + 255) & ~(size_t)255) + 2 * kCostBuckets * sizeof(uint32_t);
+}
 hipError_t launch_tile_schedule(const RenderParams& p, void* work, hipStream_t stream);
 
 // Tile shape of a wave: 16 x 4 pixels for a pinhole camera, whose rows near the horizon differ more
@@ -177,6 +183,7 @@ struct salf_context {
   std::mutex mu;
   std::vector<salf::Scene> scenes;
   int servers = 0;  // live servers on this context (under mu); the context outlives them
+  void* static_sched = nullptr;  // device address of the library's own schedule array on `device`
 };
 
 namespace salf {

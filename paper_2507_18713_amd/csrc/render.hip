@@ -388,7 +388,6 @@ __device__ __forceinline__ int find_item(const BatchItem* items, int32_t n_items
 // block and bucket).  Ties are placed in arbitrary order, which changes the schedule only, never
 // a ray's result.  A launch whose tiles all fit on the GPU at once keeps its own order (sorting
 // would only crowd the heavy tiles onto the same compute units): its schedule holds no order.
-constexpr int kCostBuckets = 256;
 
 // Header of the schedule buffer: [0] tiles (0 = no order), [1] tiled | tw_log2 << 8, [2] img_w,
 // [3] offset of the order (int32 entries after the header); then keys, order, histogram, cursors.
@@ -840,10 +839,6 @@ hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stre
 namespace {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
-
-size_t tile_work_bytes(int64_t n_tiles) {
-  return kSchedHeader * 4 + 2 * align256((size_t)n_tiles * 4) + 2 * kCostBuckets * sizeof(uint32_t);
-}
 
 namespace {
 // Schedule of the tiles of one launch (items == nullptr: p's tiles) or of a batch of requests.

@@ -1,0 +1,97 @@
+"""The render entry point that allocates nothing (salf_render_static): the tile schedule is built in
+the library's own per-device array instead of a caller buffer.  Called through the C ABI twice in a
+row (the second launch smaller, so it reuses the array over the first one's stale contents), each
+result equal bit for bit to salf_render with the schedule built in a caller buffer (the same kernels;
+outputs never depend on the tile order); a launch larger than the array is refused before any work.
+"""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+OUTS = ("rgb", "depth", "opacity", "t_end", "n_hits")
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def salf():
+    import paper_2507_18713_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def scene(salf):
+    # a 12 x 10 x 4 m adaptive block centred on (3, 2.5, 0), seen from outside: each camera below
+    # renders thousands of tiles, enough that the heaviest-first order is built (more tiles than
+    # the GPU holds at once)
+    data = synth.random_scene(411, root_dims=(12, 10, 4), max_level=3, root_size=1.0, fill=0.6)
+    return salf.Scene.from_data(data, device=_dev(), preactivate=True)
+
+
+def _c_render(salf, entry, scene, sensor):
+    """One render through the C ABI: salf_render with SALF_SCHEDULE_BUILD into a fresh caller
+    buffer, or salf_render_static (no buffer).  Outputs start as NaN / -1 so unwritten rays show."""
+    from paper_2507_18713_amd import _lib
+    from paper_2507_18713_amd.api import sensor_struct
+    L = _lib.lib()
+    dev = _dev()
+    n = sensor["width"] * sensor["height"]
+    res = {k: torch.full((n, 3) if k == "rgb" else (n,), -1 if k == "n_hits" else math.nan,
+                         dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev) for k in OUTS}
+    ob = _lib.Outputs()
+    for k in _lib.Outputs._fields_:
+        setattr(ob, k[0], res[k[0]].data_ptr() if k[0] in res else None)
+    sen = sensor_struct(sensor)
+    opts = _lib.RenderOpts()
+    opts.samples_per_voxel, opts.t_min = 4, 1e-6
+    opts.background[:] = [0.1, 0.2, 0.3]
+    work = None
+    if entry == "salf_render":
+        nb = C.c_size_t()
+        assert L.salf_render_work_size(C.byref(sen), None, C.byref(nb)) == 0
+        work = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        opts.schedule, opts.d_work, opts.work_bytes = _lib.SCHEDULE_BUILD, work.data_ptr(), work.numel()
+    else:  # whatever the opts say about a buffer is ignored
+        opts.schedule, opts.d_work, opts.work_bytes = _lib.SCHEDULE_REUSE, None, 0
+    stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    st = getattr(L, entry)(scene.ctx.handle, scene.id, C.byref(sen), None, C.byref(opts), C.byref(ob), stream)
+    assert st == 0, (entry, st, L.salf_last_error())
+    torch.cuda.synchronize()
+    return res
+
+
+def test_static_schedule_render_equals_the_buffered_one(salf, scene):
+    eye_a, eye_b = (-9.0, -7.0, 5.0), (15.0, 12.0, 3.0)
+    big = synth.pinhole(1920, 1080, 75.0, synth.look_at(eye_a, (3.0, 2.5, 0.0)), eye_a)
+    small = synth.pinhole(640, 512, 60.0, synth.look_at(eye_b, (3.0, 2.5, 0.5)), eye_b)
+    for sensor in (big, small):
+        print(f"salf_render_static {sensor['width']}x{sensor['height']}", flush=True)
+        got = _c_render(salf, "salf_render_static", scene, sensor)
+        ref = _c_render(salf, "salf_render", scene, sensor)
+        assert int((ref["n_hits"] > 0).sum()) > sensor["width"] * sensor["height"] // 4
+        for k in OUTS:
+            assert not torch.any(torch.isnan(got[k].float())), k
+            assert torch.equal(got[k], ref[k]), (sensor["width"], k)
+
+
+def test_static_schedule_refuses_a_launch_larger_than_its_array(salf, scene):
+    from paper_2507_18713_amd import _lib
+    from paper_2507_18713_amd.api import sensor_struct
+    L = _lib.lib()
+    # 8,192 x 2,080 pixels in 16 x 4 tiles = 266,240 tiles > 2^18: refused on the host, nothing runs
+    sen = sensor_struct(synth.pinhole(8192, 2080, 60.0, np.eye(3), (0.0, 0.0, -20.0)))
+    opts = _lib.RenderOpts()
+    opts.samples_per_voxel, opts.t_min = 4, 1e-6
+    ob = _lib.Outputs()
+    st = L.salf_render_static(scene.ctx.handle, scene.id, C.byref(sen), None, C.byref(opts), C.byref(ob), None)
+    assert st == -2, st  # OUT_OF_MEMORY
+    assert b"static schedule" in L.salf_last_error()
