@@ -86,7 +86,8 @@ enum {
   SALF_ERR_NOT_FOUND = -4,     /* unknown scene id or ticket                                        */
   SALF_ERR_BUDGET = -5,        /* a serving request alone exceeds the server's memory budget        */
   SALF_ERR_BUSY = -6,          /* the object still has work in flight                               */
-  SALF_ERR_UNSUPPORTED = -7    /* a valid but unimplemented combination                             */
+  SALF_ERR_UNSUPPORTED = -7,   /* a valid but unimplemented combination                             */
+  SALF_ERR_TRUNCATED = -8      /* salf_sync: some ray ran out of its traversal step budget           */
 };
 
 enum { SALF_FIELD_CORNER = 0, SALF_FIELD_PAPER = 1, SALF_FIELD_SDF = 2 };
@@ -115,8 +116,18 @@ salf_status salf_create(int32_t hip_device, salf_context** out);
  * Errors: INVALID_ARG, BUSY (a server created on it is still alive). */
 salf_status salf_destroy(salf_context* ctx);
 
-/* Synchronize `stream` and report any fault raised by kernels enqueued on it. Errors: DEVICE. */
+/* Synchronize `stream` and report any fault raised by kernels enqueued on it.  Also reports rays
+ * that were cut short: every walk of a ray through a scene (render, backward, trace) takes at most
+ * the context's step budget of steps (root-grid steps, leaf passes and octree descents together);
+ * a ray that runs out composites only the hits found so far, and the first salf_sync of each
+ * context on the device after such a launch has finished returns TRUNCATED with the number of such
+ * rays since its previous report (the count is kept per device).  Errors: DEVICE, TRUNCATED. */
 salf_status salf_sync(salf_context* ctx, void* stream);
+
+/* Steps a ray's walk may take before it is cut short (default 2^22, far beyond any scene's needs:
+ * a walk is bounded by the grid and the voxels it crosses).  Applies to calls made after this one;
+ * mainly a diagnostic (a small budget forces the cut-short report).  Errors: INVALID_ARG (< 1). */
+salf_status salf_set_step_budget(salf_context* ctx, int32_t steps);
 
 /* ------------------------------------------------------------------ scenes (Sec. 3.1, 3.2) */
 
@@ -199,8 +210,9 @@ salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t 
 
 /* Densification and pruning of a scene's voxel set (Sec. 3.3), producing the voxels and parameters
  * of a new scene (the caller builds it with salf_scene_create).  Voxel v is
- *   pruned  if its largest opacity 1 - exp(-sigma_max edge) is below alpha_min (the paper: 0.001),
- *           sigma_max being the largest of its 8 corner densities (where every field mode peaks);
+ *   pruned  if its edge opacity 1 - exp(-sigma_max edge) is below alpha_min (the paper: 0.001), the
+ *           opacity of a path one edge long at sigma_max, the largest of its 8 corner densities
+ *           (where every field mode peaks); the paper does not say which opacity it thresholds;
  *   split   else, if level < K and the L1 norm of its colour-field gradient (all 24 colour logits
  *           of the corner field; rgb[ch][0:3] of the paper and SDF fields) exceeds grad_threshold,
  *           into its 8 octree-aligned children (child b = bx + 2 by + 4 bz at (2i + bx, 2j + by,
@@ -360,6 +372,61 @@ salf_status salf_render_static(salf_context* ctx, int32_t scene_id, const salf_s
                                const salf_rays* rays, const salf_render_opts* opts, const salf_outputs* out,
                                void* stream);
 
+/* Several sensor renders in one launch: the 64-ray tiles of every item go out in one launch whose
+ * waves pull tiles from a shared counter, ordered heaviest first across all items when they number
+ * at most 2^17 (item order otherwise), so the long tiles of one sensor (a LiDAR's) start first and
+ * the others' fill in around them.  Each item renders to the same bits as salf_render of it (the
+ * same device function renders a tile).  Vehicles carry many sensors rendered at one time (Sec. 1).
+ * Corner-field scenes only (raw or pre-activated), sensors only (no explicit rays). */
+typedef struct {
+  int32_t scene_id;
+  int32_t reserved;             /* must be 0 */
+  const salf_sensor* sensor;    /* read during the call */
+  salf_render_opts opts;        /* samples, t_min, background; the schedule fields are not used */
+  salf_outputs out;             /* as salf_render */
+} salf_render_item;
+
+/* Device bytes of salf_render_multi's work area for n_items items.  Errors: INVALID_ARG. */
+salf_status salf_render_multi_work_size(int32_t n_items, size_t* bytes);
+
+/* Render n_items (1..256) items in one launch on `stream`.  d_work: caller memory (256-byte aligned)
+ * of salf_render_multi_work_size bytes, not shared by launches that may overlap.  Errors:
+ * INVALID_ARG, NOT_FOUND, UNSUPPORTED (a paper-field or SDF scene), DEVICE. */
+salf_status salf_render_multi(salf_context* ctx, int32_t n_items, const salf_render_item* items, void* d_work,
+                              size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ tile-based splatting (Sec. 3.2) */
+/* Rasterization of a global-shutter pinhole frame ("Tile-based Splatting", Sec. 3.2): every voxel
+ * is projected (its eight corners; culled when wholly behind the camera or off the image) and
+ * listed under each 16 x 16-pixel tile its footprint rectangle overlaps (widened by a pixel; a voxel
+ * reaching within 1 cm of the camera plane is listed under every tile); each tile's list is sorted
+ * front to back; one workgroup per tile stages its voxels' boxes and parameter rows in LDS, and
+ * each lane (one pixel) composites the voxels its ray meets under the interval rule, in list
+ * order, with the shading and compositing of salf_render (Eq. 1-4).  The depth order is the
+ * front-to-back order of the voxel grid seen from the eye (root cells by L1 distance from the
+ * eye's root cell, then octant by octant relative to the eye's side of each mid-plane), which is
+ * each pixel ray's own hit order, so the outputs are the same bits as salf_render of the sensor.
+ * The paper sorts by depth without saying which; a centre-depth order would composite some
+ * neighbouring voxels out of order.  A (voxel, tile) pair is one list entry. */
+
+/* Device bytes of salf_render_raster's work area for a frame of `sensor` on scene `scene_id` with
+ * up to max_pairs pairs (typically 1-4 per visible voxel).  Uses the device (the sort's temporary
+ * storage depends on it).  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (not a global-shutter
+ * pinhole), DEVICE. */
+salf_status salf_raster_work_size(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, int64_t max_pairs,
+                                  size_t* bytes);
+
+/* Render `sensor` by splatting.  sensor: SALF_PINHOLE whose rays share one pose (dt_line == 0, or v
+ * and w zero); opts: samples, t_min and background as salf_render (the schedule fields are
+ * ignored); out: as salf_render.  d_work: caller memory (256-byte aligned) of work_bytes.  The call
+ * blocks once on `stream` to read the pair count back (the sort's size) and stores it in *n_pairs;
+ * if the work area cannot hold that many pairs, nothing is rendered and OUT_OF_MEMORY is returned
+ * (size it with salf_raster_work_size(*n_pairs) and call again).  The rest runs asynchronously on
+ * `stream`.  Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+salf_status salf_render_raster(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                               const salf_render_opts* opts, const salf_outputs* out, void* d_work, size_t work_bytes,
+                               int64_t* n_pairs, void* stream);
+
 /* ------------------------------------------------------------------ dynamic actors */
 /* An actor: a scene in its own canonical frame placed by a rigid pose, a world point p being the
  * actor point R^T (p - t) (R row-major, orthonormal). */
@@ -386,12 +453,20 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
                                   const salf_actor* actors, const salf_sensor* sensor, const salf_rays* rays,
                                   const salf_render_opts* opts, const salf_outputs* out, void* stream);
 
-/* The voxels each explicit ray hits, front to back, with no early termination:
- *   d_counts int32 [n]: total hits of the ray (may exceed max_hits)
+/* The voxels each explicit ray hits, front to back (Sec. 3.2: the ray-voxel segments a render
+ * composites):
+ *   apply_early_termination 0: every hit of the ray (opts is not read);
+ *                           1: the ray stops after the voxel that leaves T < opts->t_min, with
+ *                              opts->samples_per_voxel samples per voxel and transmittance composited
+ *                              exactly as salf_render does (only the density decides it), so the
+ *                              list is the one a render of these rays shades and d_counts equals its
+ *                              n_hits
+ *   d_counts int32 [n]: hits of the ray (may exceed max_hits)
  *   d_ids int32 [n, max_hits]: voxel ids (upload index); d_t_in, d_t_out float [n, max_hits]
  * Entries past a ray's count are left untouched.  Errors: INVALID_ARG, NOT_FOUND, DEVICE. */
 salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
-                            int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream);
+                            int32_t apply_early_termination, const salf_render_opts* opts, int32_t* d_counts,
+                            int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream);
 
 /* ------------------------------------------------------------------ differentiation (Eq. 7) */
 
@@ -463,8 +538,11 @@ salf_status salf_server_request_bytes(const salf_sensor* sensor, uint32_t output
  * and must outlive the server.  Errors: INVALID_ARG, DEVICE. */
 salf_status salf_server_create(salf_context* ctx, const salf_server_opts* opts, salf_server** out);
 
-/* Queue a render of `sensor` on scene `scene_id` (corner field) with `opts`.  Non-blocking; the
- * scene must stay alive until the request completes.  *ticket identifies the request.
+/* Queue a render of `sensor` on scene `scene_id` (corner field) with `opts`.  Non-blocking.  The
+ * render runs on the server's own streams: work the caller enqueued on another stream that changes
+ * the scene (parameter updates, salf_scene_refresh) must have finished before this call (synchronize
+ * that stream first).  The scene (its workspace, index and parameter buffers) must stay alive and
+ * unchanged until the request is done.  *ticket identifies the request.
  * Errors: INVALID_ARG, NOT_FOUND, UNSUPPORTED (paper or SDF field), BUDGET (its outputs alone exceed the
  * pool). */
 salf_status salf_server_submit(salf_server* server, int32_t scene_id, const salf_sensor* sensor,

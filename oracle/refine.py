@@ -1,8 +1,11 @@
 """Densification and pruning of the sparse voxel set (Sec. 3.3), float64 — test infrastructure.
 
 For each voxel v of level l (edge s0 / 2^l metres):
-  prune     if its largest opacity alpha_max = 1 - exp(-sigma_max s0 / 2^l) is below alpha_min
-            (Sec. 3.3 uses 0.001).  sigma_max is the largest density inside the voxel; in every
+  prune     if its edge opacity alpha_e = 1 - exp(-sigma_max s0 / 2^l) is below alpha_min
+            (Sec. 3.3 uses 0.001): the opacity of a path one edge long at the voxel's largest
+            density (a reading: the paper does not say which opacity; the longest chord of the
+            cube is sqrt(3) edges, so this is not the largest opacity a ray can see in the voxel).
+            sigma_max is the largest density inside the voxel; in every
             field mode it is reached at a corner (a trilinear interpolation of non-negative corner
             values, exp of an affine form, or Eq. 6's density, monotone in an affine s), so it is the
             largest of the eight corner densities.

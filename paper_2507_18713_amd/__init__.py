@@ -6,9 +6,10 @@ Importing it loads the library and fails loudly if it is not built.
 """
 from ._lib import SalfError, lib as _load_lib, LIB_PATH
 from .api import (Context, Scene, RenderFunction, Server, generate_rays, ray_count, render, render_backward,
-                  render_composite, render_schedule, sensor_struct, trace_hits)
+                  render_composite, render_multi, render_raster, render_schedule, sensor_struct, trace_hits)
 
 _load_lib()
 
 __all__ = ["SalfError", "LIB_PATH", "Context", "Scene", "RenderFunction", "Server", "generate_rays", "ray_count",
-           "render", "render_backward", "render_composite", "render_schedule", "sensor_struct", "trace_hits"]
+           "render", "render_backward", "render_composite", "render_multi", "render_raster", "render_schedule", "sensor_struct",
+           "trace_hits"]

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libsalf.so")
 
 SALF_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUDGET",
-                -6: "BUSY", -7: "UNSUPPORTED"}
+                -6: "BUSY", -7: "UNSUPPORTED", -8: "TRUNCATED"}
 FIELD_CORNER, FIELD_PAPER, FIELD_SDF = 0, 1, 2
 SCENE_PREACTIVATE = 1
 SCHEDULE_NONE, SCHEDULE_BUILD, SCHEDULE_REUSE = 0, 1, 2
@@ -63,6 +63,11 @@ class Outputs(C.Structure):
                 ("t_end", C.c_void_p), ("n_hits", C.c_void_p)]
 
 
+class RenderItem(C.Structure):
+    _fields_ = [("scene_id", C.c_int32), ("reserved", C.c_int32), ("sensor", C.POINTER(Sensor)),
+                ("opts", RenderOpts), ("out", Outputs)]
+
+
 class GradsIn(C.Structure):
     _fields_ = [("d_rgb", C.c_void_p), ("d_depth", C.c_void_p), ("d_opacity", C.c_void_p),
                 ("d_intensity", C.c_void_p)]
@@ -108,11 +113,19 @@ SIGNATURES = {
                                 C.POINTER(Outputs), C.c_void_p]),
     "salf_render_static": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
                                        C.POINTER(RenderOpts), C.POINTER(Outputs), C.c_void_p]),
+    "salf_raster_work_size": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.c_int64,
+                                          C.POINTER(C.c_size_t)]),
+    "salf_render_raster": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(RenderOpts),
+                                       C.POINTER(Outputs), C.c_void_p, C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
+    "salf_render_multi_work_size": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "salf_render_multi": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "salf_render_work_size": (C.c_int32, [C.POINTER(Sensor), C.POINTER(Rays), C.POINTER(C.c_size_t)]),
     "salf_render_schedule": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
                                          C.POINTER(RenderOpts), C.c_void_p]),
-    "salf_trace_hits": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Rays), C.c_int32, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "salf_trace_hits": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Rays), C.c_int32, C.c_int32,
+                                    C.POINTER(RenderOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    "salf_set_step_budget": (C.c_int32, [C.c_void_p, C.c_int32]),
     "salf_render_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Sensor), C.POINTER(Rays),
                                          C.POINTER(RenderOpts), C.POINTER(Outputs), C.POINTER(GradsIn), C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),

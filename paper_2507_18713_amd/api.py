@@ -51,7 +51,13 @@ class Context:
         return cls._cache[idx]
 
     def sync(self):
+        """Synchronize the current stream; raises SalfError (TRUNCATED) if a ray of an earlier
+        launch ran out of its traversal step budget."""
         call("salf_sync", self.handle, _stream(self.device))
+
+    def set_step_budget(self, steps: int):
+        """Walk steps a ray may take before it is cut short (default 2^22)."""
+        call("salf_set_step_budget", self.handle, int(steps))
 
 
 def sensor_struct(s: dict) -> _lib.Sensor:
@@ -166,7 +172,7 @@ class Scene:
                    preactivate, DEFAULT_INDEX_LEVEL if index_level is None else index_level)
 
     def refine(self, grad_rgb: Optional[torch.Tensor], grad_threshold: float, alpha_min: float = 1e-3) -> dict:
-        """Densify and prune (Sec. 3.3; salf_refine): voxels whose largest opacity is below
+        """Densify and prune (Sec. 3.3; salf_refine): voxels whose edge opacity is below
         alpha_min are dropped, voxels whose colour-field gradient (L1) exceeds grad_threshold are
         split into 8 children carrying their field, the rest kept.  Returns the new scene's device
         arrays {voxels, geo, rgb, intensity} (build it with Scene(...))."""
@@ -347,6 +353,96 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     return res
 
 
+_MULTI_WORK: Dict[tuple, torch.Tensor] = {}
+
+
+def render_multi(items, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
+                 work: Optional[torch.Tensor] = None):
+    """Render several sensors in one launch (salf_render_multi): items is a list of (scene, sensor,
+    outputs) where outputs is a tuple of output names or a dict of preallocated tensors.  Returns a
+    list of output dicts, each the same bits as render() of that item."""
+    if not items:
+        return []
+    dev = items[0][0].device
+    ctx = items[0][0].ctx
+    arr = (_lib.RenderItem * len(items))()
+    keep, results = [], []
+    for i, (scene, sensor, outputs) in enumerate(items):
+        n = ray_count(sensor)
+        res = dict(outputs) if isinstance(outputs, dict) else {}
+        for k in (outputs.keys() if isinstance(outputs, dict) else outputs):
+            if k not in OUTPUT_NAMES:
+                raise ValueError(f"unknown output {k}")
+            if k not in res:
+                shape = (n, 3) if k == "rgb" else (n,)
+                res[k] = torch.empty(shape, dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev)
+        sen = sensor_struct(sensor)
+        keep.append(sen)
+        arr[i].scene_id = scene.id
+        arr[i].reserved = 0
+        arr[i].sensor = C.pointer(sen)
+        arr[i].opts = _opts(samples, t_min, background)
+        for k in OUTPUT_NAMES:
+            setattr(arr[i].out, k, res[k].data_ptr() if k in res else None)
+        results.append(res)
+    if work is None:
+        nb = C.c_size_t()
+        call("salf_render_multi_work_size", len(items), C.byref(nb))
+        key = (dev.index, len(items), torch.cuda.current_stream(dev).cuda_stream)
+        work = _MULTI_WORK.get(key)
+        if work is None or work.numel() < int(nb.value):
+            work = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+            _MULTI_WORK[key] = work
+    call("salf_render_multi", ctx.handle, len(items), arr, _ptr(work), int(work.numel()), _stream(dev))
+    return results
+
+
+def render_raster(scene: Scene, sensor: dict, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
+                  outputs: Iterable[str] = ("rgb", "depth", "opacity"), out: Optional[Dict[str, torch.Tensor]] = None,
+                  work: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+    """Render a global-shutter pinhole `sensor` by tile-based splatting (salf_render_raster): the
+    same outputs, bit for bit, as render() of the sensor.  The call blocks once (it reads the
+    frame's (voxel, tile) pair count back); the work area is kept on the scene and grown as frames
+    need.  `work` overrides it."""
+    dev = scene.device
+    outputs = tuple(outputs)
+    for k in outputs:
+        if k not in OUTPUT_NAMES:
+            raise ValueError(f"unknown output {k}")
+    sen = sensor_struct(sensor)
+    n = ray_count(sensor)
+    res = {} if out is None else dict(out)
+    for k in outputs:
+        if k not in res:
+            shape = (n, 3) if k == "rgb" else (n,)
+            res[k] = torch.empty(shape, dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev)
+    ob = _lib.Outputs()
+    for k in OUTPUT_NAMES:
+        setattr(ob, k, res[k].data_ptr() if k in res else None)
+    opts = _opts(samples, t_min, background)
+    pairs = C.c_int64()
+    for attempt in range(2):
+        buf = work if work is not None else getattr(scene, "_raster_work", None)
+        if buf is None:
+            nb = C.c_size_t()
+            call("salf_raster_work_size", scene.ctx.handle, scene.id, C.byref(sen),
+                 max(4 * scene.n, 1 << 16) if attempt == 0 else int(pairs.value * 1.25) + 1024, C.byref(nb))
+            buf = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+            if work is None:
+                scene._raster_work = buf
+        st = _lib.lib().salf_render_raster(scene.ctx.handle, scene.id, C.byref(sen), C.byref(opts), C.byref(ob),
+                                           _ptr(buf), int(buf.numel()), C.byref(pairs), _stream(dev))
+        if st == _lib.ERR_OUT_OF_MEMORY and work is None and attempt == 0:
+            scene._raster_work = None
+            continue
+        if st != _lib.SALF_OK:
+            msg = _lib.lib().salf_last_error()
+            raise _lib.SalfError(st, "salf_render_raster", msg.decode() if msg else "")
+        break
+    scene.raster_pairs = int(pairs.value)
+    return res
+
+
 def render_composite(scene: Scene, actors, sensor: Optional[dict] = None, o: Optional[torch.Tensor] = None,
                      d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6,
                      background=(0.0, 0.0, 0.0), outputs: Iterable[str] = ("rgb", "depth", "opacity"),
@@ -387,9 +483,11 @@ def render_composite(scene: Scene, actors, sensor: Optional[dict] = None, o: Opt
 
 
 def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_near: float = 0.0,
-               t_far: float = math.inf):
+               t_far: float = math.inf, early_termination: bool = False, samples: int = 4, t_min: float = 1e-6):
     """Voxels hit by each ray, front to back: counts [n] and ids/t_in/t_out [n, max_hits]
-    (entries past a ray's count are -1 / NaN)."""
+    (entries past a ray's count are -1 / NaN).  early_termination: stop each ray after the voxel
+    that leaves T < t_min with `samples` samples per voxel, as a render does (counts then equal the
+    render's n_hits)."""
     dev = scene.device
     rays = _rays_struct(o, d, t_near, t_far, dev)
     n = int(rays.n)
@@ -397,8 +495,8 @@ def trace_hits(scene: Scene, o: torch.Tensor, d: torch.Tensor, max_hits: int, t_
     ids = torch.full((n, max_hits), -1, dtype=torch.int32, device=dev)
     ti = torch.full((n, max_hits), float("nan"), dtype=torch.float32, device=dev)
     to = torch.full((n, max_hits), float("nan"), dtype=torch.float32, device=dev)
-    call("salf_trace_hits", scene.ctx.handle, scene.id, C.byref(rays), int(max_hits), _ptr(counts), _ptr(ids),
-         _ptr(ti), _ptr(to), _stream(dev))
+    call("salf_trace_hits", scene.ctx.handle, scene.id, C.byref(rays), int(max_hits), int(bool(early_termination)),
+         C.byref(_opts(samples, t_min, (0.0, 0.0, 0.0))), _ptr(counts), _ptr(ids), _ptr(ti), _ptr(to), _stream(dev))
     return counts, ids, ti, to
 
 
@@ -454,18 +552,27 @@ class RenderFunction(torch.autograd.Function):
             want.append("intensity")
         res = render(scene, sensor=sensor, o=o, d=d, outputs=want, **opts)
         ctx.scene, ctx.sensor, ctx.o, ctx.d, ctx.opts = scene, sensor, o, d, opts
-        ctx.saved = res
         empty = torch.empty(0, device=geo.device)
-        ctx.mark_non_differentiable(res["t_end"], res["n_hits"])
-        return res.get("rgb", empty), res["depth"], res["opacity"], res.get("intensity", empty)
+        outs = (res.get("rgb", empty), res["depth"], res["opacity"], res.get("intensity", empty))
+        # the backward reads the parameters in place and the forward's outputs (its suffix sums are
+        # formed from them), so both go through autograd's saved-tensor version checks: an in-place
+        # change of either before backward raises instead of corrupting the gradient
+        ctx.save_for_backward(geo, rgb, intensity, *outs, res["t_end"], res["n_hits"])
+        return outs
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_opacity, g_int):
         sc = ctx.scene
+        _, _, _, o_rgb, o_depth, o_opacity, o_int, t_end, n_hits = ctx.saved_tensors
+        saved = {"depth": o_depth, "opacity": o_opacity, "t_end": t_end, "n_hits": n_hits}
+        if o_rgb.numel():
+            saved["rgb"] = o_rgb
+        if o_int.numel():
+            saved["intensity"] = o_int
         grads = {"rgb": g_rgb if sc.rgb is not None and g_rgb is not None and g_rgb.numel() else None,
                  "depth": g_depth, "opacity": g_opacity,
                  "intensity": g_int if sc.intensity is not None and g_int is not None and g_int.numel() else None}
-        dg, dr, di = render_backward(sc, ctx.saved, grads, sensor=ctx.sensor, o=ctx.o, d=ctx.d, **ctx.opts)
+        dg, dr, di = render_backward(sc, saved, grads, sensor=ctx.sensor, o=ctx.o, d=ctx.d, **ctx.opts)
         return dg, dr, di, None, None, None, None, None
 
 
@@ -507,11 +614,16 @@ class Server:
 
     def submit(self, scene: Scene, sensor: dict, outputs=("rgb", "depth", "opacity"), samples: int = 4,
                t_min: float = 1e-6, background=(0.0, 0.0, 0.0)) -> int:
+        """Queue a render (on the server's own streams: synchronize the stream of any pending change
+        to the scene first).  The scene's device buffers are held until release(), so dropping the
+        Scene (or rebuilding its index) while the request is in flight cannot free memory the kernel
+        reads."""
         t = C.c_uint64()
         mask = sum(_OUT_BITS[k] for k in outputs)
         call("salf_server_submit", self.handle, scene.id, C.byref(sensor_struct(sensor)),
              C.byref(_opts(samples, t_min, background)), mask, C.byref(t))
-        self._meta[int(t.value)] = (tuple(outputs), int(sensor["width"]) * int(sensor["height"]))
+        held = (scene, scene.workspace, scene.index, scene.geo, scene.rgb, scene.intensity)
+        self._meta[int(t.value)] = (tuple(outputs), int(sensor["width"]) * int(sensor["height"]), held)
         return int(t.value)
 
     def poll(self, ticket: int):
@@ -523,7 +635,7 @@ class Server:
              C.byref(td))
         if not done.value:
             return None
-        outs, n = self._meta[ticket]
+        outs, n, _ = self._meta[ticket]
         base = self.pool.data_ptr()
         res = {}
         for k in outs:

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libsalf.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "scene_build.hip", "render.hip", "server.hip"]
+SOURCES = ["api.hip", "scene_build.hip", "render.hip", "server.hip", "raster.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: no packed FP32 VALU instructions (kept scalar on purpose).

@@ -127,6 +127,7 @@ salf_status salf::scene_snapshot(salf_context* ctx, int32_t id, Scene* out) {
   if (id < 0 || id >= (int32_t)ctx->scenes.size() || !ctx->scenes[id].live)
     return set_error(SALF_ERR_NOT_FOUND, "no scene with id %d", id);
   *out = ctx->scenes[id];
+  out->view.step_budget = ctx->step_budget;
   return SALF_OK;
 }
 
@@ -291,7 +292,25 @@ salf_status salf_sync(salf_context* ctx, void* stream) {
   DeviceGuard g(ctx->device);
   salf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
   if (st) return st;
-  return check_hip(hipGetLastError(), "kernel execution");
+  if ((st = check_hip(hipGetLastError(), "kernel execution"))) return st;
+  uint32_t total = 0;
+  if ((st = check_hip(read_cut_rays((hipStream_t)stream, &total), "reading the cut-ray count"))) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (total != ctx->cut_seen) {
+    const uint32_t fresh = total - ctx->cut_seen;
+    ctx->cut_seen = total;
+    return set_error(SALF_ERR_TRUNCATED, "%u ray(s) ran out of their traversal step budget (%d steps) and were cut short",
+                     fresh, ctx->step_budget);
+  }
+  return SALF_OK;
+}
+
+salf_status salf_set_step_budget(salf_context* ctx, int32_t steps) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  if (steps < 1) return set_error(SALF_ERR_INVALID_ARG, "the step budget must be >= 1");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->step_budget = steps;
+  return SALF_OK;
 }
 
 salf_status salf_scene_workspace_size(const salf_scene_desc* desc, int64_t n_voxels, size_t* bytes) {
@@ -352,6 +371,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
   v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
   v.rbox = (const uint2*)((char*)d_workspace + L.rbox_off);
+  v.vbox = (const int4*)((char*)d_workspace + L.vbox_off);
   v.boff = nullptr;
   v.cidx = nullptr;
   v.act_geo = v.act_rgb = v.act_int = nullptr;
@@ -551,6 +571,147 @@ salf_status salf_render_static(salf_context* ctx, int32_t scene_id, const salf_s
   return salf_render(ctx, scene_id, sensor, rays, &o, out, stream);
 }
 
+}  // extern "C"
+
+namespace {
+// The splatting parameters of a frame of `sensor` on scene `scene_id`.
+salf_status raster_setup(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, RasterParams* p, int* field) {
+  Scene sc;
+  salf_status st = scene_snapshot(ctx, scene_id, &sc);
+  if (st) return st;
+  if ((st = validate_sensor(sensor))) return st;
+  if (sensor->model != SALF_PINHOLE) return set_error(SALF_ERR_UNSUPPORTED, "splatting renders pinhole cameras");
+  const bool still = sensor->v[0] == 0.0f && sensor->v[1] == 0.0f && sensor->v[2] == 0.0f && sensor->w[0] == 0.0f &&
+                     sensor->w[1] == 0.0f && sensor->w[2] == 0.0f;
+  if (sensor->dt_line != 0.0f && !still)
+    return set_error(SALF_ERR_UNSUPPORTED, "splatting needs one pose for every pixel (no rolling-shutter motion)");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(sensor->p0[i])) return set_error(SALF_ERR_INVALID_ARG, "sensor position is not finite");
+  memset(p, 0, sizeof(*p));
+  p->scene = sc.view;
+  p->sensor = *sensor;
+  p->n_voxels = sc.n;
+  raster_prepare(p);
+  if (p->key_bits + p->tile_bits > 64)
+    return set_error(SALF_ERR_UNSUPPORTED, "the frame's tiles and the scene's grid need more than 64 key bits");
+  *field = sc.desc.field;
+  return SALF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+salf_status salf_raster_work_size(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor, int64_t max_pairs,
+                                  size_t* bytes) {
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  if (max_pairs < 0 || max_pairs > (int64_t)UINT32_MAX)
+    return set_error(SALF_ERR_INVALID_ARG, "max_pairs must be in [0, 2^32)");
+  RasterParams p;
+  int field = 0;
+  salf_status st = raster_setup(ctx, scene_id, sensor, &p, &field);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  return check_hip(raster_work_bytes(p.n_voxels, (int64_t)p.tiles_x * p.tiles_y, max_pairs, bytes),
+                   "splatting work size");
+}
+
+salf_status salf_render_raster(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
+                               const salf_render_opts* opts, const salf_outputs* out, void* d_work, size_t work_bytes,
+                               int64_t* n_pairs, void* stream) {
+  RasterParams p;
+  int field = 0;
+  salf_status st = raster_setup(ctx, scene_id, sensor, &p, &field);
+  if (st) return st;
+  if ((st = validate_opts(opts))) return st;
+  if (!out || !n_pairs) return set_error(SALF_ERR_INVALID_ARG, "outputs and n_pairs are required");
+  if (out->rgb && !p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
+  if (out->intensity && !p.scene.inten)
+    return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
+  if (!d_work || ((uintptr_t)d_work & 255u)) return set_error(SALF_ERR_INVALID_ARG, "work area must be 256-byte aligned");
+  p.S = opts->samples_per_voxel;
+  p.t_min = opts->t_min;
+  for (int c = 0; c < 3; ++c) p.bg[c] = opts->background[c];
+  p.out = *out;
+  DeviceGuard g(ctx->device);
+  int64_t pairs = 0, cap = 0;
+  if ((st = check_hip(launch_raster(p, field, d_work, work_bytes, &pairs, &cap, (hipStream_t)stream),
+                      "splatting launch")))
+    return st;
+  *n_pairs = pairs;
+  if (pairs > cap)
+    return set_error(SALF_ERR_OUT_OF_MEMORY, "the frame has %lld (voxel, tile) pairs; the work area holds %lld",
+                     (long long)pairs, (long long)cap);
+  return SALF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+constexpr int32_t kMultiMax = 256;
+inline size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Work area of a multi-sensor launch: [items][tile counter][batch schedule].
+size_t multi_bytes(int32_t n) {
+  return up256((size_t)n * sizeof(BatchItem)) + 256 + up256(tile_work_bytes(kBatchScheduleTiles));
+}
+}  // namespace
+
+extern "C" {
+
+salf_status salf_render_multi_work_size(int32_t n_items, size_t* bytes) {
+  if (!bytes) return set_error(SALF_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_items < 1 || n_items > kMultiMax) return set_error(SALF_ERR_INVALID_ARG, "n_items must be in [1, %d]", kMultiMax);
+  *bytes = multi_bytes(n_items);
+  return SALF_OK;
+}
+
+salf_status salf_render_multi(salf_context* ctx, int32_t n_items, const salf_render_item* items, void* d_work,
+                              size_t work_bytes, void* stream) {
+  if (!ctx) return set_error(SALF_ERR_INVALID_ARG, "context is NULL");
+  if (n_items < 1 || n_items > kMultiMax || !items)
+    return set_error(SALF_ERR_INVALID_ARG, "n_items must be in [1, %d] with items", kMultiMax);
+  if (!d_work || ((uintptr_t)d_work & 255u) || work_bytes < multi_bytes(n_items))
+    return set_error(SALF_ERR_INVALID_ARG, "work area must be 256-byte aligned and hold %zu bytes", multi_bytes(n_items));
+  std::vector<BatchItem> batch((size_t)n_items);
+  int64_t tiles = 0;
+  uint32_t variants = 0;
+  salf_status st;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const salf_render_item& it = items[i];
+    if (it.reserved != 0 || !it.sensor) return set_error(SALF_ERR_INVALID_ARG, "item %d: reserved != 0 or no sensor", i);
+    BatchItem& b = batch[(size_t)i];
+    memset(&b, 0, sizeof(b));
+    salf_render_opts o = it.opts;
+    o.schedule = SALF_SCHEDULE_NONE;
+    int field = 0;
+    if ((st = prepare_render(ctx, it.scene_id, it.sensor, nullptr, &o, &b.p, &field))) return st;
+    if (field != SALF_FIELD_CORNER) return set_error(SALF_ERR_UNSUPPORTED, "item %d: multi-sensor launches render corner-field scenes", i);
+    if (it.out.rgb && !b.p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "item %d: colour from a scene without colour", i);
+    if (it.out.intensity && !b.p.scene.inten)
+      return set_error(SALF_ERR_INVALID_ARG, "item %d: intensity from a scene without intensity", i);
+    b.p.out = it.out;
+    b.tile_begin = tiles;
+    b.variant = (it.out.rgb ? 1 : 0) | (it.out.intensity ? 2 : 0) | (b.p.scene.act_geo ? 4 : 0);
+    variants |= 1u << b.variant;
+    tiles += tile_count(b.p);
+    if (tiles > ((int64_t)1 << 31)) return set_error(SALF_ERR_INVALID_ARG, "more than 2^31 tiles in one launch");
+  }
+  char* w = (char*)d_work;
+  BatchItem* d_items = (BatchItem*)w;
+  uint32_t* d_counter = (uint32_t*)(w + up256((size_t)n_items * sizeof(BatchItem)));
+  void* d_sched = w + up256((size_t)n_items * sizeof(BatchItem)) + 256;
+  DeviceGuard g(ctx->device);
+  const hipStream_t s = (hipStream_t)stream;
+  static const uint32_t zero = 0;
+  if ((st = check_hip(hipMemcpyAsync(d_items, batch.data(), batch.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s),
+                      "multi-sensor items copy")))
+    return st;
+  if ((st = check_hip(hipMemcpyAsync(d_counter, &zero, sizeof(zero), hipMemcpyHostToDevice, s), "counter reset")))
+    return st;
+  if ((st = check_hip(launch_batch_schedule(d_items, n_items, tiles, d_sched, s), "multi-sensor schedule"))) return st;
+  return check_hip(launch_render_batch(d_items, n_items, tiles, d_counter, (const int32_t*)d_sched, variants, s),
+                   "multi-sensor launch");
+}
+
 salf_status salf_render_schedule(salf_context* ctx, int32_t scene_id, const salf_sensor* sensor,
                                  const salf_rays* rays, const salf_render_opts* opts, void* stream) {
   if (!opts) return set_error(SALF_ERR_INVALID_ARG, "render opts is NULL");
@@ -623,7 +784,8 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
 }
 
 salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays* rays, int32_t max_hits,
-                            int32_t* d_counts, int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream) {
+                            int32_t apply_early_termination, const salf_render_opts* opts, int32_t* d_counts,
+                            int32_t* d_ids, float* d_t_in, float* d_t_out, void* stream) {
   Scene sc;
   salf_status st = scene_snapshot(ctx, scene_id, &sc);
   if (st) return st;
@@ -631,8 +793,17 @@ salf_status salf_trace_hits(salf_context* ctx, int32_t scene_id, const salf_rays
   if (max_hits < 0) return set_error(SALF_ERR_INVALID_ARG, "max_hits must be >= 0");
   if (rays->n > 0 && (!d_counts || (max_hits > 0 && (!d_ids || !d_t_in || !d_t_out))))
     return set_error(SALF_ERR_INVALID_ARG, "output pointer is NULL");
+  int field = -1, S = 1;
+  float t_min = 0.0f;
+  if (apply_early_termination) {
+    if ((st = validate_opts(opts))) return st;
+    field = sc.desc.field;
+    S = opts->samples_per_voxel;
+    t_min = opts->t_min;
+  }
   DeviceGuard g(ctx->device);
-  return check_hip(launch_trace(sc.view, *rays, max_hits, d_counts, d_ids, d_t_in, d_t_out, (hipStream_t)stream),
+  return check_hip(launch_trace(sc.view, *rays, max_hits, field, S, t_min, d_counts, d_ids, d_t_in, d_t_out,
+                                (hipStream_t)stream),
                    "trace launch");
 }
 

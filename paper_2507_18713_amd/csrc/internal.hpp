@@ -18,7 +18,7 @@ salf_status set_error(salf_status code, const char* fmt, ...);
 salf_status check_hip(hipError_t e, const char* what);
 
 // ---- scene workspace layout: [root grid][skip grid][levels][root bounds][nodes][node bounds][bounds scratch][hash keys]
-//      [hash values][2 temp grids][counters][activated corner values, pre-activated scenes only]
+//      [hash values][2 temp grids][counters][voxel boxes][activated corner values, pre-activated scenes only]
 struct SceneLayout {
   int64_t n_root;        // root cells
   int64_t node_cap;      // internal nodes the workspace can hold
@@ -27,6 +27,7 @@ struct SceneLayout {
   size_t order_off;  // node-numbering temporaries (0 when the scene can have no nodes)
   size_t lmax_off;   // finest voxel level per root cell
   size_t rbox_off;   // bounds of each root cell's voxels (uint2 per cell, zero for cells without a node)
+  size_t vbox_off;   // each voxel's finest-cell box (int4: min corner, edge), for splatting
   size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
   size_t total;
 };
@@ -152,9 +153,46 @@ hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_
 constexpr int64_t kBatchScheduleTiles = (int64_t)1 << 17;
 hipError_t launch_batch_schedule(const BatchItem* d_items, int32_t n_items, int64_t n_tiles, void* work,
                                  hipStream_t stream);
-hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int32_t* counts, int32_t* ids,
-                        float* t_in, float* t_out, hipStream_t stream);
+// field < 0: every hit; else (the scene's field) stop after the voxel that leaves T < t_min, with S
+// samples per voxel, as the render does.
+hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int field, int32_t S, float t_min,
+                        int32_t* counts, int32_t* ids, float* t_in, float* t_out, hipStream_t stream);
+// Total of rays cut short by their step budget on the current device since the library was loaded
+// (read on `stream`, which is synchronized).
+hipError_t read_cut_rays(hipStream_t stream, uint32_t* total);
+// Default steps of a ray's walk (root steps, leaf passes and descents together) before it is cut short.
+constexpr int32_t kDefaultStepBudget = 1 << 22;
 hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uint8_t* valid, hipStream_t stream);
+
+// Tile-based splatting of a global-shutter pinhole frame (raster.hip).
+struct RasterParams {
+  SceneView scene;
+  salf_sensor sensor;
+  int64_t n_voxels;
+  int32_t width, height, tiles_x, tiles_y;
+  int32_t S;
+  float t_min;
+  float bg[3];
+  salf_outputs out;
+  double R[9], eye[3], fx, fy, cx, cy;  // camera pose and intrinsics for the projection (FP64)
+  float og[3];                          // the eye in the FP32 grid frame of the interval rule
+  int32_t eye_root[3];                  // its root cell, clamped to [-1, dims]
+  int32_t key_bits, tile_bits;          // bits of the depth key and of the tile index in a pair key
+  uint32_t* count;                      // [n_voxels + 1] tiles per voxel
+  uint64_t* offset;                     // [n_voxels + 1] their exclusive scan
+  uint64_t* keys;                       // [pairs] tile << key_bits | depth key
+  uint32_t* vals;                       // [pairs] voxel
+};
+// Fill the derived fields of p (eye, camera, tiling, key widths) from p->scene and p->sensor.
+void raster_prepare(RasterParams* p);
+// Work-area bytes for n voxels, n_tiles tiles and max_pairs pairs (queries the sort's temporary
+// storage for the current device).
+hipError_t raster_work_bytes(int64_t n_voxels, int64_t n_tiles, int64_t max_pairs, size_t* bytes);
+// Render p's frame; blocks once on `stream` to read the pair count into *n_pairs and renders
+// nothing when it exceeds *capacity, the pairs the work area holds.
+hipError_t launch_raster(RasterParams p, int field, void* work, size_t work_bytes, int64_t* n_pairs,
+                         int64_t* capacity, hipStream_t stream);
+int64_t raster_capacity(int64_t n_voxels, int64_t n_tiles, size_t work_bytes);
 
 struct BackwardParams {
   RenderParams fwd;
@@ -184,6 +222,8 @@ struct salf_context {
   std::vector<salf::Scene> scenes;
   int servers = 0;  // live servers on this context (under mu); the context outlives them
   void* static_sched = nullptr;  // device address of the library's own schedule array on `device`
+  int32_t step_budget = salf::kDefaultStepBudget;  // per-ray walk steps (salf_set_step_budget)
+  uint32_t cut_seen = 0;  // rays cut short on the device already reported by this context's salf_sync
 };
 
 namespace salf {

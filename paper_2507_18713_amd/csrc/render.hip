@@ -10,128 +10,19 @@
 #include <atomic>
 
 #include "internal.hpp"
+#include "shade.hpp"
 
 namespace salf {
 namespace {
 
 constexpr int kThreads = 256;
 
-// Composited state of one ray.
-struct Accum {
-  float T, C[3], D, I;
-  int32_t n;
-};
-
-// Shade one voxel segment [ti, to] and composite it into acc.  Returns false once the ray has
-// become opaque enough to stop (T < t_min after the voxel).
-// Density of the SDF variant (Eq. 6) at signed distance q: a/2 + a/2 sign(q) (1 - exp(-|q| / b)),
-// with ha = a / 2 and ib = 1 / b.
-__device__ __forceinline__ float sdf_sigma(float q, float ha, float ib) {
-  const float m = ha * (1.0f - __expf(-fabsf(q) * ib));
-  return q > 0.0f ? ha + m : (q < 0.0f ? ha - m : ha);
-}
-
-template <int FIELD, bool RGB, bool INT>
-__device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
-                                            int S, double rS, float t_min, Accum& acc) {
-  const int32_t v = h.voxel;
-  const float ti = h.t_in;
-  // corner parameters of the voxel (coalescing across lanes comes from coherent rays)
-  constexpr bool kAct = FIELD == kFieldCornerActivated;
-  const float* geo = kAct ? s.act_geo : s.geo;
-  const float* rgb = kAct ? s.act_rgb : s.rgb;
-  const float* itn = kAct ? s.act_int : s.inten;
-  float g[8], c[3][8], it[8];
-  {
-    const float4* gp = reinterpret_cast<const float4*>(geo + (int64_t)v * 8);
-    const float4 g0 = gp[0], g1 = gp[1];
-    g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w; g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
-  }
-  if (RGB) {
-    const float4* cp = reinterpret_cast<const float4*>(rgb + (int64_t)v * 24);
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      const float4 a = cp[2 * ch], b = cp[2 * ch + 1];
-      c[ch][0] = a.x; c[ch][1] = a.y; c[ch][2] = a.z; c[ch][3] = a.w;
-      c[ch][4] = b.x; c[ch][5] = b.y; c[ch][6] = b.z; c[ch][7] = b.w;
-    }
-  }
-  if (INT) {
-    const float4* ip = reinterpret_cast<const float4*>(itn + (int64_t)v * 8);
-    const float4 a = ip[0], b = ip[1];
-    it[0] = a.x; it[1] = a.y; it[2] = a.z; it[3] = a.w; it[4] = b.x; it[5] = b.y; it[6] = b.z; it[7] = b.w;
-  }
-  // the paper field (and its SDF variant) evaluates affine forms of x; the corner fields
-  // interpolate corner values
-  constexpr bool kAffine = FIELD == SALF_FIELD_PAPER || FIELD == kFieldSdf;
-  float shc[3] = {0.0f, 0.0f, 0.0f};  // view-dependent colour term (paper field)
-  float sdf_ha = 0.0f, sdf_ib = 0.0f;  // SDF variant: a / 2 and 1 / b
-  if (FIELD == kFieldSdf) {
-    sdf_ha = 0.5f * __expf(g[4]);
-    sdf_ib = __expf(-g[5]);
-  }
-  if (FIELD == SALF_FIELD_CORNER) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) g[i] = softplus_f(g[i]);
-    if (RGB) {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) c[ch][i] = sigmoid_f(c[ch][i]);
-    }
-    if (INT) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) it[i] = sigmoid_f(it[i]);
-    }
-  } else if (kAffine && RGB) {
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
-      shc[ch] = fmaf(c[ch][3], sh[0], fmaf(c[ch][4], sh[1], fmaf(c[ch][5], sh[2], c[ch][6] * sh[3])));
-  }
-
-  float rel[3], stp[3], delta, sc;
-  segment_frame(s, f, h, rS, rel, stp, delta, sc);
-
-  for (int k = 0; k < S; ++k) {
-    const float fk = (float)k + 0.5f;
-    float u[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
-    float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-    if (!kAffine) {
-      float w[8];
-      corner_weights(u, w);
-      sigma = dot8(w, g);
-      if (RGB) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, c[ch]);
-      }
-      if (INT) inten = dot8(w, it);
-    } else {
-      float x[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
-      const float q = fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3])));
-      sigma = FIELD == kFieldSdf ? sdf_sigma(q, sdf_ha, sdf_ib) : __expf(q);
-      if (RGB) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-          col[ch] = sigmoid_f(fmaf(c[ch][0], x[0], fmaf(c[ch][1], x[1], fmaf(c[ch][2], x[2], shc[ch]))));
-      }
-      if (INT) inten = sigmoid_f(fmaf(it[0], x[0], fmaf(it[1], x[1], fmaf(it[2], x[2], it[3]))));
-    }
-    const float e = __expf(-sigma * delta);
-    const float wgt = acc.T * (1.0f - e);
-    if (RGB) {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc.C[ch] = fmaf(wgt, col[ch], acc.C[ch]);
-    }
-    acc.D = fmaf(wgt, fmaf(fk, delta, ti), acc.D);
-    if (INT) acc.I = fmaf(wgt, inten, acc.I);
-    acc.T *= e;
-  }
-  acc.n += 1;
-  return !(acc.T < t_min);
+// Rays whose walk ran out of its step budget on this device, since the library was loaded (never
+// reset; read by salf_sync).  Walks are cut short only on pathological input, so the atomic is
+// off the hot path.
+__device__ uint32_t g_cut_rays;
+__device__ __forceinline__ void note_cut(bool whole) {
+  if (!whole) atomicAdd(&g_cut_rays, 1u);
 }
 
 // The ray of this lane of wave `wave` (tiled: the wave's tile; else 64 consecutive rays): its
@@ -199,9 +90,9 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const int S = p.S;
   const double rS = 1.0 / S;
   const float t_min = p.t_min;
-  traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
+  note_cut(traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
     return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
-  });
+  }));
   const salf_outputs& out = p.out;
   if (out.rgb) {
 #pragma unroll
@@ -351,10 +242,10 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
         actor_ray(cp.slot[k], o, d, oa, da);
       }
       const RayFrame fr = make_frame(sv, oa, da, t0, t1);
-      traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+      note_cut(traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
         alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
         return alive;
-      });
+      }));
     }
     if (!alive) ray_done = true;
   }
@@ -513,8 +404,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MASK =
   }
 }
 
-__global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays r, int32_t max_hits, int32_t* counts,
-                                                         int32_t* ids, float* t_in, float* t_out) {
+// Hit lists of explicit rays.  FIELD >= 0: with the render's early termination, each ray stopping
+// after the voxel that leaves T < t_min, T composited exactly as the render composites it (the
+// density alone decides it); FIELD < 0: every hit.
+template <int FIELD>
+__global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays r, int32_t max_hits, int32_t S,
+                                                         float t_min, int32_t* counts, int32_t* ids, float* t_in,
+                                                         float* t_out) {
   const int64_t ray = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (ray >= r.n) return;
   float o[3], d[3];
@@ -527,15 +423,23 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays 
   int32_t n = 0;
   const int64_t base = ray * (int64_t)max_hits;
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
-  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  const float sh[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const double rS = 1.0 / S;
+  Accum acc;
+  acc.T = 1.0f;
+  acc.C[0] = acc.C[1] = acc.C[2] = 0.0f;
+  acc.D = acc.I = 0.0f;
+  acc.n = 0;
+  note_cut(traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     if (n < max_hits) {
       ids[base + n] = h.voxel;
       t_in[base + n] = h.t_in;
       t_out[base + n] = h.t_out;
     }
     ++n;
+    if constexpr (FIELD >= 0) return shade_voxel<FIELD, false, false>(s, f, sh, h, S, rS, t_min, acc);
     return true;
-  });
+  }));
   counts[ray] = n;
 }
 
@@ -608,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   // degree-1 SH basis of the ray direction (paper field), as in the forward
   const float shb[4] = {kShC0, kShC1 * dir[0], kShC1 * dir[1], kShC1 * dir[2]};
-  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  note_cut(traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
     // activated corner values (stored ones when the scene keeps them, else from the logits); for
@@ -821,7 +725,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       if (dst) unsafeAtomicAdd(dst, sum);
     }
     return ++count < n_stop;
-  });
+  }));
 }
 
 template <int FIELD>
@@ -994,12 +898,30 @@ hipError_t launch_backward(const BackwardParams& b, int field, hipStream_t strea
   return hipGetLastError();
 }
 
-hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int32_t* counts, int32_t* ids,
-                        float* t_in, float* t_out, hipStream_t stream) {
+hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int field, int32_t S, float t_min,
+                        int32_t* counts, int32_t* ids, float* t_in, float* t_out, hipStream_t stream) {
   if (r.n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((r.n + kThreads - 1) / kThreads);
-  trace_kernel<<<blocks, kThreads, 0, stream>>>(s, r, max_hits, counts, ids, t_in, t_out);
+  if (field < 0)
+    trace_kernel<-1><<<blocks, kThreads, 0, stream>>>(s, r, max_hits, S, t_min, counts, ids, t_in, t_out);
+  else if (field == SALF_FIELD_PAPER)
+    trace_kernel<SALF_FIELD_PAPER><<<blocks, kThreads, 0, stream>>>(s, r, max_hits, S, t_min, counts, ids, t_in, t_out);
+  else if (field == SALF_FIELD_SDF)
+    trace_kernel<kFieldSdf><<<blocks, kThreads, 0, stream>>>(s, r, max_hits, S, t_min, counts, ids, t_in, t_out);
+  else if (s.act_geo != nullptr)
+    trace_kernel<kFieldCornerActivated><<<blocks, kThreads, 0, stream>>>(s, r, max_hits, S, t_min, counts, ids, t_in,
+                                                                         t_out);
+  else
+    trace_kernel<SALF_FIELD_CORNER><<<blocks, kThreads, 0, stream>>>(s, r, max_hits, S, t_min, counts, ids, t_in,
+                                                                     t_out);
   return hipGetLastError();
+}
+
+hipError_t read_cut_rays(hipStream_t stream, uint32_t* total) {
+  hipError_t e = hipMemcpyFromSymbolAsync(total, HIP_SYMBOL(g_cut_rays), sizeof(uint32_t), 0, hipMemcpyDeviceToHost,
+                                          stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
 }
 
 hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uint8_t* valid, hipStream_t stream) {

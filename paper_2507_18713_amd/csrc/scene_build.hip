@@ -122,6 +122,15 @@ __global__ void insert_kernel(BuildArgs a) {
   }
 }
 
+// Each voxel's finest-cell box: min corner and edge (2^(K - l) cells).
+__global__ void vbox_kernel(const int32_t* vox, int64_t n, int K, int4* vbox) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int4 q = reinterpret_cast<const int4*>(vox)[v];
+  const int sh = K - q.x;
+  vbox[v] = make_int4(q.y << sh, q.z << sh, q.w << sh, 1 << sh);
+}
+
 // d0(v) <- l_v (no node yet), 0 for an invalid voxel
 __global__ void d0_init(BuildArgs a) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -393,6 +402,8 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
   }
   L->counters_off = off;
   off = up(off + sizeof(BuildCounters));
+  L->vbox_off = off;
+  off = up(off + (size_t)n * 16);
   L->act_geo_off = L->act_rgb_off = L->act_int_off = 0;
   if (d.flags & SALF_SCENE_PREACTIVATE) {
     L->act_geo_off = off;
@@ -709,6 +720,8 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
   }
   count_roots<<<blocks_for(L.n_root, T) > 1024 ? 1024 : blocks_for(L.n_root, T), T, 0, stream>>>(a.root, L.n_root,
                                                                                                   a.cnt);
+  // (a voxel outside [0, K] fails the build before its box is read)
+  if (n > 0) vbox_kernel<<<blocks_for(n, T), T, 0, stream>>>(voxels, n, a.K, (int4*)(base + L.vbox_off));
   return hipGetLastError();
 }
 

@@ -97,9 +97,10 @@ def test_workspace_size_host_logic(L):
     assert n.value > small
     # a K = 0 scene needs no nodes: the root grid and the finest-level grid (4 B per cell each),
     # the root-bounds grid (8 B per cell), the skip-distance grid and its two build-time
-    # temporaries (1 B per cell each), a minimal hash table and the counters
+    # temporaries (1 B per cell each), each voxel's box (16 B per voxel), a minimal hash table and
+    # the counters
     assert lib.salf_scene_workspace_size(C.byref(_desc(L, dims=(32, 32, 32), K=0)), 4096, C.byref(n)) == 0
-    assert 32 ** 3 * 19 <= n.value < 32 ** 3 * 19 + 64 * 1024
+    assert 32 ** 3 * 19 + 4096 * 16 <= n.value < 32 ** 3 * 19 + 4096 * 16 + 64 * 1024
     # invalid descriptions
     for bad in (_desc(L, K=9), _desc(L, s0=0.0), _desc(L, s0=math.nan), _desc(L, dims=(0, 4, 4)),
                 _desc(L, dims=(1 << 17, 4, 4), K=4), _desc(L, field=7)):

@@ -304,6 +304,13 @@ def test_autograd_function(salf):
     assert torch.allclose(dg, scene.geo.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(dr, scene.rgb.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(di, scene.intensity.grad, rtol=1e-4, atol=1e-6)
+    # the backward reads the returned outputs: changing one in place before backward is an error,
+    # not a silently wrong gradient
+    rgb, depth, op, inten = salf.RenderFunction.apply(scene.geo, scene.rgb, scene.intensity, scene, None,
+                                                      to_dev(o), to_dev(d), opts)
+    rgb.clamp_(0.0, 0.5)
+    with pytest.raises(RuntimeError, match="inplace"):
+        (rgb.sum() + depth.sum()).backward()
 
 
 def test_preactivated_scene_gives_the_same_gradient(salf):

@@ -1,0 +1,154 @@
+"""Tile-based splatting on the GPU (salf_render_raster) against the CPU oracle's splatting and the
+ray cast of the same camera.
+
+With the front-to-back octree key every pixel composites its own ray's hits in their order, so
+the splatted frame must equal salf_render of the same sensor bit for bit (the same interval rule
+and shading arithmetic), and the oracle's splatting to the stated tolerance.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle.render import RenderOpts
+
+from test_gpu_render import TOL_C, TOL_D, dev
+
+pytestmark = pytest.mark.gpu
+OUTS = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def salf():
+    import paper_2507_18713_amd as m
+    return m
+
+
+def _cameras(data, w=40, h=30):
+    lo = np.asarray(data.origin, np.float64)
+    ext = np.asarray(data.root_dims, np.float64) * data.root_size
+    c = lo + ext / 2
+    s0 = data.root_size
+    eyes = [(c + np.array([1.3, -1.1, 0.7]) * ext.max(), c, 70.0),
+            (c + np.array([0.05, 0.02, 1.5]) * ext.max(), c, 60.0),
+            (lo + np.array([0.37, 0.41, 0.33]) * ext, c + np.array([0.2, 0.1, 0.05]) * ext, 100.0),
+            (lo + np.array([2.0, 1.5, 1.0]) * s0, c + np.array([0.3, 0.2, -0.1]) * ext, 90.0),
+            (lo + np.array([1.5, 2.25, 0.5]) * s0, lo + np.array([0.9, 0.2, 0.8]) * ext, 90.0)]
+    return [synth.pinhole(w, h, fov, synth.look_at(e, t), e) for e, t, fov in eyes]
+
+
+def _equal(a, b, keys):
+    for k in keys:
+        assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("seed,K", [(301, 1), (302, 2), (303, 3)])
+def test_raster_matches_the_oracle_splatting(salf, seed, K):
+    data = synth.random_scene(seed, root_dims=(5, 4, 3), max_level=K, fill=0.7)
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev())
+    for i, (cam, (S, tmin, bg)) in enumerate(zip(_cameras(data), [(4, 1e-6, (0.1, 0.2, 0.3)), (1, 0.0, (0, 0, 0)),
+                                                                    (4, 1e-2, (0.5, 0.5, 0.5)), (1, 1e-6, (0, 0, 0)),
+                                                                    (2, 1e-6, (0.2, 0.1, 0.0))])):
+        print(f"splatting seed {seed} K {K} camera {i}", flush=True)
+        got = salf.render_raster(scene, cam, samples=S, t_min=tmin, background=bg, outputs=OUTS)
+        ref, _ = oracle.raster(ps, cam, RenderOpts(samples=S, t_min=tmin, background=bg))
+        for k in OUTS:
+            g = got[k].cpu().numpy().astype(np.float64)
+            if k == "n_hits":
+                assert np.array_equal(g, ref[k]), k
+                continue
+            err = float(np.max(np.abs(g - ref[k])))
+            assert err <= (TOL_D if k == "depth" else TOL_C), (k, err)
+        assert int(got["n_hits"].sum()) > 200
+
+
+@pytest.mark.parametrize("field,preact", [("corner", False), ("corner", True), ("paper", False), ("sdf", False)])
+def test_raster_equals_the_ray_cast_bit_for_bit(salf, field, preact):
+    """Every field variant, ragged image sizes, eyes inside and outside the grid, with and without
+    early termination: splatting and ray casting give the same bits."""
+    data = synth.random_scene(331, root_dims=(6, 5, 4), max_level=3, fill=0.8)
+    if field != "corner":
+        rng = np.random.default_rng(332)
+        g = np.zeros_like(data.z_geo)
+        g[:, :3] = rng.normal(0, 0.5, (data.n, 3))
+        g[:, 3] = rng.normal(0.0, 1.0, data.n)
+        if field == "sdf":
+            g[:, 4] = rng.normal(0.5, 0.3, data.n)
+            g[:, 5] = rng.normal(-1.0, 0.3, data.n)
+        data.z_geo = g.astype(F32)
+        rgb = np.zeros_like(data.z_rgb)
+        rgb[:, :, :7] = rng.normal(0, 0.5, (data.n, 3, 7))
+        data.z_rgb = rgb.astype(F32)
+    scene = salf.Scene.from_data(data, device=dev(), field=field, preactivate=preact)
+    for cam in _cameras(data, 100, 75) + _cameras(data, 33, 17)[:2]:
+        for S, tmin in ((4, 1e-6), (1, 0.0), (3, 1e-2)):
+            a = salf.render_raster(scene, cam, samples=S, t_min=tmin, background=(0.3, 0.2, 0.1), outputs=OUTS)
+            b = salf.render(scene, sensor=cam, samples=S, t_min=tmin, background=(0.3, 0.2, 0.1), outputs=OUTS)
+            _equal(a, b, OUTS)
+
+
+def test_raster_driving_frame_equals_the_ray_cast(salf):
+    """The driving scene's 1920x1080 frame (pre-activated, as timed) and a smaller raw-logit frame."""
+    data = synth.config1_scene()
+    pre = salf.Scene.from_data(data, device=dev(), preactivate=True)
+    cam = synth.config1_camera()
+    outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
+    a = salf.render_raster(pre, cam, outputs=outs)
+    b = salf.render(pre, sensor=cam, outputs=outs)
+    print(f"driving frame: {pre.raster_pairs} (voxel, tile) pairs", flush=True)
+    assert pre.raster_pairs > data.n // 4
+    _equal(a, b, outs)
+    del pre
+    raw = salf.Scene.from_data(data, device=dev())
+    small = synth.config1_camera(480, 270)
+    _equal(salf.render_raster(raw, small, outputs=outs), salf.render(raw, sensor=small, outputs=outs), outs)
+
+
+def test_raster_work_area_and_unsupported_sensors(salf):
+    from paper_2507_18713_amd import _lib
+    from paper_2507_18713_amd.api import _opts, sensor_struct
+    data = synth.random_scene(341, root_dims=(6, 5, 4), max_level=2)
+    scene = salf.Scene.from_data(data, device=dev())
+    cam = _cameras(data, 64, 48)[0]
+    ref = salf.render(scene, sensor=cam, outputs=("rgb", "n_hits"))
+    L = _lib.lib()
+    sen = sensor_struct(cam)
+    n = 64 * 48
+    rgb = torch.full((n, 3), float("nan"), device=dev())
+    ob = _lib.Outputs()
+    ob.rgb = rgb.data_ptr()
+    nb = C.c_size_t()
+    assert L.salf_raster_work_size(scene.ctx.handle, scene.id, C.byref(sen), 8, C.byref(nb)) == 0
+    small = torch.empty(int(nb.value), dtype=torch.uint8, device=dev())
+    pairs = C.c_int64()
+    st = L.salf_render_raster(scene.ctx.handle, scene.id, C.byref(sen), C.byref(_opts(4, 1e-6, (0, 0, 0))),
+                              C.byref(ob), small.data_ptr(), small.numel(), C.byref(pairs), None)
+    torch.cuda.synchronize()
+    assert st == -2 and pairs.value > 8 and torch.all(torch.isnan(rgb))   # refused, nothing rendered
+    assert L.salf_raster_work_size(scene.ctx.handle, scene.id, C.byref(sen), pairs.value, C.byref(nb)) == 0
+    big = torch.empty(int(nb.value), dtype=torch.uint8, device=dev())
+    st = L.salf_render_raster(scene.ctx.handle, scene.id, C.byref(sen), C.byref(_opts(4, 1e-6, (0, 0, 0))),
+                              C.byref(ob), big.data_ptr(), big.numel(), C.byref(pairs), None)
+    torch.cuda.synchronize()
+    assert st == 0 and torch.equal(rgb, ref["rgb"])
+    # rolling shutter with motion, fisheye and LiDAR sensors have no single eye: refused
+    moving = dict(cam, dt_line=1e-4, v=[1.0, 0.0, 0.0])
+    for bad in (moving, synth.fisheye_equidistant(64, 48, 190.0, np.eye(3), (0, 0, 0)),
+                synth.lidar_spinning(8, 32, -25, 15, np.eye(3), (0, 0, 0), 0.1)):
+        with pytest.raises(salf.SalfError, match="UNSUPPORTED"):
+            salf.render_raster(scene, bad)
+    # a still rolling-shutter camera has one eye: accepted, same bits as the ray cast
+    still = dict(cam, dt_line=1e-4)
+    _equal(salf.render_raster(scene, still, outputs=("rgb", "n_hits")),
+           salf.render(scene, sensor=still, outputs=("rgb", "n_hits")), ("rgb", "n_hits"))
+    # an empty scene renders the background
+    empty = synth.random_scene(342, root_dims=(2, 2, 2), max_level=1, fill=0.0)
+    es = salf.Scene.from_data(empty, device=dev())
+    r = salf.render_raster(es, cam, background=(0.25, 0.5, 0.75), outputs=("rgb", "opacity", "n_hits"))
+    assert torch.all(r["rgb"] == torch.tensor([0.25, 0.5, 0.75], device=dev()))
+    assert torch.all(r["opacity"] == 0) and torch.all(r["n_hits"] == 0)

@@ -329,6 +329,64 @@ def test_early_termination_and_max_samples(salf):
             assert np.sum(ref["n_hits"] < full["n_hits"]) > 20
 
 
+@pytest.mark.parametrize("field,preact", [("corner", False), ("corner", True), ("paper", False), ("sdf", False)])
+def test_trace_with_early_termination_lists_what_the_render_shades(salf, field, preact):
+    """salf_trace_hits with early termination: each ray's list is the prefix of its full list (the
+    oracle's, bit for bit) that the render composites, its count equal to the render's n_hits."""
+    data = synth.random_scene(56, root_dims=(6, 5, 4), max_level=2, fill=0.9)
+    if field == "corner":
+        data.z_geo = (data.z_geo + 3.0).astype(F32)      # dense: most rays stop early
+    else:                                                # affine density / SDF parameters
+        rng = np.random.default_rng(57)
+        data.z_geo = np.zeros_like(data.z_geo)
+        data.z_geo[:, :3] = rng.normal(0, 0.5, (data.n, 3))
+        data.z_geo[:, 3] = rng.normal(2.5, 0.5, data.n) if field == "paper" else rng.normal(0.5, 0.3, data.n)
+        if field == "sdf":
+            data.z_geo[:, 4] = rng.normal(2.0, 0.2, data.n)
+            data.z_geo[:, 5] = rng.normal(-1.0, 0.2, data.n)
+        data.z_geo = data.z_geo.astype(F32)
+    ps = oracle.prepare(data)
+    scene = salf.Scene.from_data(data, device=dev(), field=field, preactivate=preact)
+    o, d = synth.random_rays(58, 600, data.origin, data.origin + data.root_dims * data.root_size)
+    for S, tmin in ((4, 1e-6), (1, 1e-2)):
+        got = salf.render(scene, o=to_dev(o), d=to_dev(d), samples=S, t_min=tmin, outputs=("n_hits",))
+        cnt, ids, ti, to = salf.trace_hits(scene, to_dev(o), to_dev(d), 256, early_termination=True, samples=S,
+                                           t_min=tmin)
+        full, fids, _, _ = salf.trace_hits(scene, to_dev(o), to_dev(d), 256)
+        cnt, ids, full, fids = (x.cpu().numpy() for x in (cnt, ids, full, fids))
+        assert np.array_equal(cnt, got["n_hits"].cpu().numpy())
+        assert np.sum(cnt < full) > 50
+        for r in range(o.shape[0]):
+            e_ids, _, _ = oracle.hit_list(ps, o[r], d[r])
+            assert np.array_equal(fids[r, :full[r]], e_ids) and np.array_equal(ids[r, :cnt[r]], e_ids[:cnt[r]]), r
+
+
+def test_step_budget_cuts_rays_short_and_is_reported(salf):
+    """A tiny traversal step budget, forced from the host, cuts walks short: the kernels end normally,
+    the next sync reports how many rays were cut (once), and the default budget renders as before."""
+    data = synth.random_scene(59, root_dims=(6, 5, 4), max_level=2, fill=0.9)
+    scene = salf.Scene.from_data(data, device=dev())
+    o, d = synth.random_rays(60, 400, data.origin, data.origin + data.root_dims * data.root_size)
+    ref = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    scene.ctx.sync()
+    try:
+        scene.ctx.set_step_budget(6)
+        cut = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+        with pytest.raises(salf.SalfError, match="TRUNCATED") as err:
+            scene.ctx.sync()
+        n_cut = int(str(err.value).split(": ")[-1].split(" ")[0])
+        shorter = int((cut["n_hits"] < ref["n_hits"]).sum())
+        assert 0 < shorter <= n_cut <= o.shape[0]
+        scene.ctx.sync()                                 # reported once
+    finally:
+        scene.ctx.set_step_budget(1 << 22)
+    again = salf.render(scene, o=to_dev(o), d=to_dev(d), outputs=("rgb", "n_hits"))
+    scene.ctx.sync()
+    assert torch.equal(again["rgb"], ref["rgb"]) and torch.equal(again["n_hits"], ref["n_hits"])
+    with pytest.raises(salf.SalfError, match="INVALID_ARG"):
+        scene.ctx.set_step_budget(0)
+
+
 def test_upload_order_only_renames(salf):
     data = synth.random_scene(56)
     perm = np.random.default_rng(57).permutation(data.n)
