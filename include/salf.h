@@ -398,7 +398,7 @@ salf_status salf_render_multi(salf_context* ctx, int32_t n_items, const salf_ren
 /* ------------------------------------------------------------------ tile-based splatting (Sec. 3.2) */
 /* Rasterization of a global-shutter pinhole frame ("Tile-based Splatting", Sec. 3.2): every voxel
  * is projected (its eight corners; culled when wholly behind the camera or off the image) and
- * listed under each 16 x 16-pixel tile its footprint rectangle overlaps (widened by a pixel; a voxel
+ * listed under each 16 x 16-pixel tile its footprint rectangle overlaps (widened by 0.05 px; a voxel
  * reaching within 1 cm of the camera plane is listed under every tile); each tile's list is sorted
  * front to back; one workgroup per tile stages its voxels' boxes and parameter rows in LDS, and
  * each lane (one pixel) composites the voxels its ray meets under the interval rule, in list

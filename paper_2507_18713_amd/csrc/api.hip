@@ -371,7 +371,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.nbox = (const uint2*)((char*)d_workspace + L.nbox_off);
   v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
   v.rbox = (const uint2*)((char*)d_workspace + L.rbox_off);
-  v.vbox = (const int4*)((char*)d_workspace + L.vbox_off);
+  sc.vbox = (const int4*)((char*)d_workspace + L.vbox_off);
   v.boff = nullptr;
   v.cidx = nullptr;
   v.act_geo = v.act_rgb = v.act_int = nullptr;
@@ -581,6 +581,8 @@ salf_status raster_setup(salf_context* ctx, int32_t scene_id, const salf_sensor*
   if (st) return st;
   if ((st = validate_sensor(sensor))) return st;
   if (sensor->model != SALF_PINHOLE) return set_error(SALF_ERR_UNSUPPORTED, "splatting renders pinhole cameras");
+  if (sensor->width > 32767 || sensor->height > 32767)
+    return set_error(SALF_ERR_UNSUPPORTED, "splatting renders images of at most 32767 x 32767 pixels");
   const bool still = sensor->v[0] == 0.0f && sensor->v[1] == 0.0f && sensor->v[2] == 0.0f && sensor->w[0] == 0.0f &&
                      sensor->w[1] == 0.0f && sensor->w[2] == 0.0f;
   if (sensor->dt_line != 0.0f && !still)
@@ -589,6 +591,7 @@ salf_status raster_setup(salf_context* ctx, int32_t scene_id, const salf_sensor*
     if (!isfinite(sensor->p0[i])) return set_error(SALF_ERR_INVALID_ARG, "sensor position is not finite");
   memset(p, 0, sizeof(*p));
   p->scene = sc.view;
+  p->vbox = sc.vbox;
   p->sensor = *sensor;
   p->n_voxels = sc.n;
   raster_prepare(p);

@@ -41,7 +41,6 @@ struct SceneView {
   const int32_t* boff;   // [Dz][Dy][Dx] first entry of each root cell's dense leaf index, or -1;
                          // null: no index
   const uint32_t* cidx;  // dense leaf indexes (see kIdx* below)
-  const int4* vbox;      // [N] each voxel's finest-cell min corner (x, y, z) and edge (w)
   const float* act_geo;  // activated corner values (pre-activated corner scenes), same layouts as
   const float* act_rgb;  // geo / rgb / inten; null otherwise
   const float* act_int;
@@ -359,19 +358,19 @@ __device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f
 // Every bound is a crossing the rule itself computes.  The leaf found contains t, so its t_in
 // (the largest of its entry crossings and t_near) is exactly t, and its t_out is its exit crossing
 // capped by t_far: neither needs recomputing.  t strictly increases, and a step budget
-// (s.step_budget) bounds the walk regardless.  Returns false only when that budget ran out before
-// the walk ended (the ray was cut short); true when it left the grid, passed t_far or visit asked
-// to stop.
-template <typename Visit>
-__device__ inline bool traverse(const SceneView& s, const RayFrame& f, int32_t* stk, int stride, Visit&& visit) {
-  if (!f.valid) return true;
+// (s.step_budget) bounds the walk regardless; a walk that runs out of it ends early and calls
+// cut() (off the hot path: only there), so the ray's truncation is reported, not silent.
+template <typename Visit, typename Cut>
+__device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* stk, int stride, Visit&& visit,
+                                Cut&& cut) {
+  if (!f.valid) return;
   const int K = s.K;
   float t, t_exit;
   {
     const int32_t glo[3] = {0, 0, 0};
     const int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
-    if (!box_interval(f, glo, ghi, t, t_exit)) return true;
-    if (!(t < t_exit)) return true;
+    if (!box_interval(f, glo, ghi, t, t_exit)) return;
+    if (!(t < t_exit)) return;
   }
   RootAxis ax, ay, az;
   root_axis_init<0>(f, s, t, ax);
@@ -398,8 +397,8 @@ __device__ inline bool traverse(const SceneView& s, const RayFrame& f, int32_t* 
       const float cell_end = fminf(cell_exit, b_out);
       if (!meets) tc = cell_end;
       if (bo >= 0) {
-        if (!index_walk(s, f, lo, s.lmax[lin], s.cidx + bo, tc, cell_end, budget, h, visit)) return true;
-        if (budget < 0) return false;  // the cell's walk ran out of steps (a failed check leaves -1)
+        if (!index_walk(s, f, lo, s.lmax[lin], s.cidx + bo, tc, cell_end, budget, h, visit)) return;
+        if (budget <= 0) break;  // the cell's walk used up the budget: the ray is cut short
       } else {
       int depth = 0;
       int32_t size = N0;
@@ -459,7 +458,7 @@ __device__ inline bool traverse(const SceneView& s, const RayFrame& f, int32_t* 
           h.size = half;
           h.t_in = tc;
           h.t_out = to;
-          if (!visit(h)) return true;
+          if (!visit(h)) return;
         }
         // (3) advance and leave every node that no longer holds tc
         if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
@@ -480,7 +479,7 @@ __device__ inline bool traverse(const SceneView& s, const RayFrame& f, int32_t* 
           c1 = np[1];
         }
       }
-      if (budget < 0) return false;
+      if (budget <= 0) break;
       }
     } else if (is_leaf_code(code)) {
       // a level-0 voxel fills the root cell: it holds t, so its interval is [t, cell_exit]
@@ -491,18 +490,18 @@ __device__ inline bool traverse(const SceneView& s, const RayFrame& f, int32_t* 
       h.size = N0;
       h.t_in = t;
       h.t_out = cell_exit;
-      if (!visit(h)) return true;
+      if (!visit(h)) return;
     } else if (dskip > 1) {  // leave the empty cube of radius dskip - 1 around this cell
       t_next = fminf(fminf(cube_exit<0>(f, s, ax, dskip), cube_exit<1>(f, s, ay, dskip)),
                      fminf(cube_exit<2>(f, s, az, dskip), t_exit));
     }
-    if (!(t_next < t_exit)) return true;
+    if (!(t_next < t_exit)) return;
     t = t_next;
     if (!root_axis_advance<0>(f, s, t, ax) || !root_axis_advance<1>(f, s, t, ay) ||
         !root_axis_advance<2>(f, s, t, az))
-      return true;
+      return;
   }
-  return false;  // the step budget ran out
+  cut();  // the step budget ran out
 }
 
 

@@ -167,6 +167,7 @@ hipError_t launch_raygen(const salf_sensor& s, float* o, float* d, float* t, uin
 // Tile-based splatting of a global-shutter pinhole frame (raster.hip).
 struct RasterParams {
   SceneView scene;
+  const int4* vbox;                     // the scene's voxel boxes
   salf_sensor sensor;
   int64_t n_voxels;
   int32_t width, height, tiles_x, tiles_y;
@@ -180,6 +181,8 @@ struct RasterParams {
   int32_t key_bits, tile_bits;          // bits of the depth key and of the tile index in a pair key
   uint32_t* count;                      // [n_voxels + 1] tiles per voxel
   uint64_t* offset;                     // [n_voxels + 1] their exclusive scan
+  uint2* rect;                          // [n_voxels] pixel rectangle: u0 | u1 << 16, r0 | r1 << 16
+  uint64_t* vkey;                       // [n_voxels] depth key
   uint64_t* keys;                       // [pairs] tile << key_bits | depth key
   uint32_t* vals;                       // [pairs] voxel
 };
@@ -211,6 +214,7 @@ struct Scene {
   int64_t n = 0;
   SceneLayout layout;
   SceneView view;
+  const int4* vbox = nullptr;  // [n] each voxel's finest-cell min corner (x, y, z) and edge (w)
   BuildCounters counters;
 };
 

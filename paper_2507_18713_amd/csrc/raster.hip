@@ -25,13 +25,17 @@ namespace {
 constexpr int kTile = 16;          // pixels per tile side (one workgroup of 256 lanes per tile)
 constexpr int kChunk = 128;        // voxels staged in LDS per round
 constexpr double kZNear = 1e-2;    // metres: a voxel reaching closer to the camera plane covers the image
-constexpr double kMargin = 1.0;    // pixels added around each projected rectangle
+// Pixels added around each projected rectangle, so that every pixel whose float32 ray meets the
+// voxel lies inside it: the rays' directions are within ~1e-6 rad of the exact pixel-centre ray
+// (a few thousandths of a pixel at the focal lengths of full-HD and 4K frames), 0.05 px is ten
+// times that.
+constexpr double kMargin = 0.05;
 
-// Inclusive tile rectangle of voxel box b (finest cells: min corner, edge), or false when culled:
+// Inclusive pixel rectangle of voxel box b (finest cells: min corner, edge), or false when culled:
 // every corner behind the camera plane, or a rectangle off the image.  A voxel reaching closer
-// than kZNear covers every tile.  FP64, with a one-pixel margin for rays that graze the voxel.
-__device__ __forceinline__ bool footprint(const RasterParams& p, const int4 b, int& tx0, int& ty0, int& tx1,
-                                          int& ty1) {
+// than kZNear covers the whole image.  FP64, widened by kMargin for rays that graze the voxel.
+__device__ __forceinline__ bool footprint(const RasterParams& p, const int4 b, int& px0, int& py0, int& px1,
+                                          int& py1) {
   const SceneView& s = p.scene;
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   bool front = false, near = false;
@@ -58,19 +62,20 @@ __device__ __forceinline__ bool footprint(const RasterParams& p, const int4 b, i
   }
   if (!front) return false;
   if (near) {
-    tx0 = ty0 = 0;
-    tx1 = p.tiles_x - 1;
-    ty1 = p.tiles_y - 1;
+    px0 = py0 = 0;
+    px1 = p.width - 1;
+    py1 = p.height - 1;
     return true;
   }
-  // pixel u has its centre at u + 1/2
-  const double u0 = floor(xmin - 0.5 - kMargin), u1 = ceil(xmax - 0.5 + kMargin);
-  const double r0 = floor(ymin - 0.5 - kMargin), r1 = ceil(ymax - 0.5 + kMargin);
+  // the pixels whose centre (u + 1/2) lies in the widened rectangle; none: no pixel ray meets it
+  const double u0 = ceil(xmin - 0.5 - kMargin), u1 = floor(xmax - 0.5 + kMargin);
+  const double r0 = ceil(ymin - 0.5 - kMargin), r1 = floor(ymax - 0.5 + kMargin);
+  if (u0 > u1 || r0 > r1) return false;
   if (u1 < 0.0 || r1 < 0.0 || u0 > (double)(p.width - 1) || r0 > (double)(p.height - 1)) return false;
-  tx0 = (int)fmax(u0, 0.0) / kTile;
-  tx1 = (int)fmin(u1, (double)(p.width - 1)) / kTile;
-  ty0 = (int)fmax(r0, 0.0) / kTile;
-  ty1 = (int)fmin(r1, (double)(p.height - 1)) / kTile;
+  px0 = (int)fmax(u0, 0.0);
+  px1 = (int)fmin(u1, (double)(p.width - 1));
+  py0 = (int)fmax(r0, 0.0);
+  py1 = (int)fmin(r1, (double)(p.height - 1));
   return true;
 }
 
@@ -102,39 +107,52 @@ __device__ __forceinline__ uint64_t depth_key(const RasterParams& p, const int4 
   return (l1 << (3 * K)) | digits;
 }
 
+// Tiles per voxel, the voxel's pixel rectangle (u0 | u1 << 16, r0 | r1 << 16: the tile kernel's
+// per-pixel pre-test, and the tiles it is listed under) and its depth key.
 __global__ void raster_count_kernel(RasterParams p) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v > p.n_voxels) return;
   uint32_t n = 0;
-  int tx0, ty0, tx1, ty1;
-  if (v < p.n_voxels && footprint(p, p.scene.vbox[v], tx0, ty0, tx1, ty1))
-    n = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  int px0, py0, px1, py1;
+  if (v < p.n_voxels && footprint(p, p.vbox[v], px0, py0, px1, py1)) {
+    n = (uint32_t)((px1 / kTile - px0 / kTile + 1) * (py1 / kTile - py0 / kTile + 1));
+    p.rect[v] = make_uint2((uint32_t)px0 | ((uint32_t)px1 << 16), (uint32_t)py0 | ((uint32_t)py1 << 16));
+    p.vkey[v] = depth_key(p, p.vbox[v]);
+  }
   p.count[v] = n;  // count[n_voxels] = 0 closes the scan
 }
 
-// The voxel's pairs, written into exactly the count[v] slots the scan gave it (the footprint is
-// recomputed by the same code; should it ever yield fewer tiles, the spare slots get the tile index
-// one past the last, which sorts after every real tile and is never rendered).
-__global__ void raster_emit_kernel(RasterParams p) {
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= p.n_voxels) return;
-  const uint32_t n = p.count[v];
-  if (n == 0) return;
-  const int4 b = p.scene.vbox[v];
-  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
-  if (!footprint(p, b, tx0, ty0, tx1, ty1)) tx1 = ty1 = -1;
-  const uint64_t key = depth_key(p, b);
-  const uint64_t at = p.offset[v];
-  uint32_t k = 0;
-  for (int ty = ty0; ty <= ty1 && k < n; ++ty)
-    for (int tx = tx0; tx <= tx1 && k < n; ++tx, ++k) {
-      p.keys[at + k] = ((uint64_t)(ty * p.tiles_x + tx) << p.key_bits) | key;
-      p.vals[at + k] = (uint32_t)v;
-    }
-  for (; k < n; ++k) {
-    p.keys[at + k] = (uint64_t)(p.tiles_x * p.tiles_y) << p.key_bits;
-    p.vals[at + k] = 0u;
+// One thread per pair: its voxel is the last one whose scan offset is at most the pair's index
+// (voxels without pairs share their successor's offset and are passed over), the pair's tile the
+// k-th of the voxel's tile rectangle, row by row.  Writes are coalesced whatever the footprints.
+__global__ void raster_emit_kernel(RasterParams p, int64_t n_pairs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_pairs) return;
+  int64_t lo = 0, hi = p.n_voxels - 1;  // offset[lo] <= i < offset[n_voxels]
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (p.offset[mid] <= (uint64_t)i) lo = mid;
+    else hi = mid - 1;
   }
+  const int64_t v = lo;
+  const uint32_t k = (uint32_t)((uint64_t)i - p.offset[v]);
+  const uint2 rc = p.rect[v];
+  const int tx0 = (int)(rc.x & 0xffffu) / kTile, tx1 = (int)(rc.x >> 16) / kTile;
+  const int ty0 = (int)(rc.y & 0xffffu) / kTile;
+  const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
+  const int tx = tx0 + (int)(k % w), ty = ty0 + (int)(k / w);
+  p.keys[i] = ((uint64_t)(ty * p.tiles_x + tx) << p.key_bits) | p.vkey[v];
+  p.vals[i] = (uint32_t)v;
+}
+
+// Tiles heaviest first: key ~(list length), so that an ascending sort puts the longest lists first
+// (the launch's tail is its longest tiles; starting them first shortens it).
+__global__ void raster_length_kernel(const uint2* range, int64_t n_tiles, uint32_t* key, uint32_t* tile) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint2 r = range[t];
+  key[t] = ~(r.y - r.x);
+  tile[t] = (uint32_t)t;
 }
 
 __global__ void raster_range_kernel(const uint64_t* keys, int64_t n_pairs, int key_bits, int64_t n_tiles,
@@ -157,10 +175,10 @@ __global__ void raster_clear_kernel(uint2* range, int64_t n) {
 // order and composites the hits; the tile stops once every pixel has stopped.
 template <int FIELD, bool RGB, bool INT>
 __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams p, const uint32_t* vals,
-                                                                     const uint2* range) {
+                                                                     const uint2* range, const uint32_t* order) {
   constexpr bool kAct = FIELD == kFieldCornerActivated;
   const SceneView& s = p.scene;
-  const int tile = blockIdx.x;
+  const int tile = (int)order[blockIdx.x];
   const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
   const int lane = threadIdx.x;
   const int col = tx * kTile + (lane % kTile), row = ty * kTile + (lane / kTile);
@@ -181,6 +199,7 @@ __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams
 
   __shared__ int32_t ids[kChunk];
   __shared__ int4 boxes[kChunk];
+  __shared__ uint2 rects[kChunk];
   __shared__ float4 rows[kChunk * 8];                   // geo [8] then rgb [3][8] per voxel
   __shared__ float4 irows[INT ? kChunk * 2 : 1];       // intensity [8] per voxel
   const float* geo = kAct ? s.act_geo : s.geo;
@@ -192,7 +211,8 @@ __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams
     if (lane < m) {
       const int32_t v = (int32_t)vals[c + lane];
       ids[lane] = v;
-      boxes[lane] = s.vbox[v];
+      boxes[lane] = p.vbox[v];
+      rects[lane] = p.rect[v];
     }
     __syncthreads();
     // 8 lanes per voxel copy its 128-byte row (2 float4 of density, 6 of colour)
@@ -209,8 +229,29 @@ __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams
         irows[q] = reinterpret_cast<const float4*>(itn + (int64_t)ids[q >> 1] * 8)[q & 1];
     }
     __syncthreads();
-    if (alive) {
-      for (int j = 0; j < m; ++j) {
+    // (1) the staged voxels whose pixel rectangle holds this pixel, as a bit mask: the same cheap
+    // test on every lane, so the wave stays converged; most listed voxels cover few of a tile's
+    // pixels.  (2) each lane then walks only its own candidates, in list order, with the interval
+    // rule and the shading: a wave pays for its busiest lane, not for the union of its lanes.
+    uint32_t cand[kChunk / 32];
+#pragma unroll
+    for (int w = 0; w < kChunk / 32; ++w) {
+      uint32_t bits = 0u;
+      for (int b = 0; b < 32; ++b) {
+        const int j = w * 32 + b;
+        const uint2 rc = rects[j];
+        const bool in = j < m && col >= (int)(rc.x & 0xffffu) && col <= (int)(rc.x >> 16) &&
+                        row >= (int)(rc.y & 0xffffu) && row <= (int)(rc.y >> 16);
+        bits |= in ? (1u << b) : 0u;
+      }
+      cand[w] = alive ? bits : 0u;
+    }
+#pragma unroll
+    for (int w = 0; w < kChunk / 32; ++w) {
+      uint32_t bits = cand[w];
+      while (bits != 0u && alive) {
+        const int j = w * 32 + (__ffs((int)bits) - 1);
+        bits &= bits - 1u;
         const int4 b = boxes[j];
         Hit h;
         h.lo[0] = b.x;
@@ -222,10 +263,7 @@ __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams
         h.voxel = ids[j];
         const float* row_p = reinterpret_cast<const float*>(rows + j * 8);
         const float* irow_p = INT ? reinterpret_cast<const float*>(irows + j * 2) : nullptr;
-        if (!shade_rows<FIELD, RGB, INT>(s, f, sh, h, S, rS, p.t_min, acc, row_p, row_p + 8, irow_p)) {
-          alive = false;
-          break;
-        }
+        if (!shade_rows<FIELD, RGB, INT>(s, f, sh, h, S, rS, p.t_min, acc, row_p, row_p + 8, irow_p)) alive = false;
       }
     }
     if (__syncthreads_count(alive ? 1 : 0) == 0) break;  // (also the barrier before the next round's loads)
@@ -245,13 +283,14 @@ __global__ __launch_bounds__(kTile * kTile) void raster_tile_kernel(RasterParams
 }
 
 template <int FIELD>
-hipError_t launch_tiles(const RasterParams& p, const uint32_t* vals, const uint2* range, hipStream_t stream) {
+hipError_t launch_tiles(const RasterParams& p, const uint32_t* vals, const uint2* range, const uint32_t* order,
+                        hipStream_t stream) {
   const unsigned blocks = (unsigned)(p.tiles_x * p.tiles_y);
   const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
-  if (rgb && in) raster_tile_kernel<FIELD, true, true><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range);
-  else if (rgb) raster_tile_kernel<FIELD, true, false><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range);
-  else if (in) raster_tile_kernel<FIELD, false, true><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range);
-  else raster_tile_kernel<FIELD, false, false><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range);
+  if (rgb && in) raster_tile_kernel<FIELD, true, true><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range, order);
+  else if (rgb) raster_tile_kernel<FIELD, true, false><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range, order);
+  else if (in) raster_tile_kernel<FIELD, false, true><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range, order);
+  else raster_tile_kernel<FIELD, false, false><<<blocks, kTile * kTile, 0, stream>>>(p, vals, range, order);
   return hipGetLastError();
 }
 
@@ -260,22 +299,30 @@ inline int bit_width(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); 
 
 // Work-area layout for n voxels, `tiles` tiles and up to `pairs` (voxel, tile) pairs.
 struct RasterLayout {
-  size_t count, offset, keys_a, keys_b, vals_a, vals_b, range, temp, temp_bytes, total;
+  size_t count, offset, rect, vkey, keys_a, keys_b, vals_a, vals_b, range, tile_sort, temp, temp_bytes, total;
 };
 
 hipError_t raster_layout(int64_t n, int64_t tiles, int64_t pairs, RasterLayout* L) {
-  size_t scan_bytes = 0, sort_bytes = 0;
+  size_t scan_bytes = 0, sort_bytes = 0, tile_bytes = 0;
   hipError_t e = rocprim::exclusive_scan(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint64_t*)nullptr,
                                          (uint64_t)0, (size_t)(n + 1), rocprim::plus<uint64_t>());
   if (e != hipSuccess) return e;
   e = rocprim::radix_sort_pairs(nullptr, sort_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                 (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)(pairs > 0 ? pairs : 1));
   if (e != hipSuccess) return e;
+  e = rocprim::radix_sort_pairs(nullptr, tile_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)(tiles > 0 ? tiles : 1));
+  if (e != hipSuccess) return e;
+  if (tile_bytes > sort_bytes) sort_bytes = tile_bytes;
   size_t off = 0;
   L->count = off;
   off = up256(off + (size_t)(n + 1) * 4);
   L->offset = off;
   off = up256(off + (size_t)(n + 1) * 8);
+  L->rect = off;
+  off = up256(off + (size_t)n * 8);
+  L->vkey = off;
+  off = up256(off + (size_t)n * 8);
   L->keys_a = off;
   off = up256(off + (size_t)pairs * 8);
   L->keys_b = off;
@@ -286,6 +333,8 @@ hipError_t raster_layout(int64_t n, int64_t tiles, int64_t pairs, RasterLayout* 
   off = up256(off + (size_t)pairs * 4);
   L->range = off;
   off = up256(off + (size_t)tiles * 8);
+  L->tile_sort = off;  // tile keys, tile ids, sorted keys, order: 4 arrays of uint32
+  off = up256(off + (size_t)tiles * 16);
   L->temp = off;
   L->temp_bytes = scan_bytes > sort_bytes ? scan_bytes : sort_bytes;
   off = up256(off + L->temp_bytes);
@@ -360,6 +409,8 @@ hipError_t launch_raster(RasterParams p, int field, void* work, size_t work_byte
   char* w = (char*)work;
   p.count = (uint32_t*)(w + L.count);
   p.offset = (uint64_t*)(w + L.offset);
+  p.rect = (uint2*)(w + L.rect);
+  p.vkey = (uint64_t*)(w + L.vkey);
   p.keys = (uint64_t*)(w + L.keys_a);
   p.vals = (uint32_t*)(w + L.vals_a);
   uint64_t* keys_b = (uint64_t*)(w + L.keys_b);
@@ -378,7 +429,7 @@ hipError_t launch_raster(RasterParams p, int field, void* work, size_t work_byte
   if ((int64_t)total > cap) return hipSuccess;  // the caller reports the shortfall
   raster_clear_kernel<<<blocks_of(tiles, T), T, 0, stream>>>(range, tiles);
   if (total > 0) {
-    raster_emit_kernel<<<blocks_of(n, T), T, 0, stream>>>(p);
+    raster_emit_kernel<<<blocks_of((int64_t)total, T), T, 0, stream>>>(p, (int64_t)total);
     tb = L.temp_bytes;
     e = rocprim::radix_sort_pairs(w + L.temp, tb, p.keys, keys_b, p.vals, vals_b, (size_t)total, 0u,
                                   (unsigned)(p.key_bits + p.tile_bits), stream);
@@ -386,10 +437,19 @@ hipError_t launch_raster(RasterParams p, int field, void* work, size_t work_byte
     raster_range_kernel<<<blocks_of((int64_t)total, T), T, 0, stream>>>(keys_b, (int64_t)total, p.key_bits, tiles,
                                                                          range);
   }
-  if (field == SALF_FIELD_PAPER) return launch_tiles<SALF_FIELD_PAPER>(p, vals_b, range, stream);
-  if (field == SALF_FIELD_SDF) return launch_tiles<kFieldSdf>(p, vals_b, range, stream);
-  if (p.scene.act_geo != nullptr) return launch_tiles<kFieldCornerActivated>(p, vals_b, range, stream);
-  return launch_tiles<SALF_FIELD_CORNER>(p, vals_b, range, stream);
+  // the tile order: longest lists first
+  uint32_t* tkey = (uint32_t*)(w + L.tile_sort);
+  uint32_t* tid = tkey + tiles;
+  uint32_t* tkey_sorted = tid + tiles;
+  uint32_t* order = tkey_sorted + tiles;
+  raster_length_kernel<<<blocks_of(tiles, T), T, 0, stream>>>(range, tiles, tkey, tid);
+  tb = L.temp_bytes;
+  e = rocprim::radix_sort_pairs(w + L.temp, tb, tkey, tkey_sorted, tid, order, (size_t)tiles, 0u, 32u, stream);
+  if (e != hipSuccess) return e;
+  if (field == SALF_FIELD_PAPER) return launch_tiles<SALF_FIELD_PAPER>(p, vals_b, range, order, stream);
+  if (field == SALF_FIELD_SDF) return launch_tiles<kFieldSdf>(p, vals_b, range, order, stream);
+  if (p.scene.act_geo != nullptr) return launch_tiles<kFieldCornerActivated>(p, vals_b, range, order, stream);
+  return launch_tiles<SALF_FIELD_CORNER>(p, vals_b, range, order, stream);
 }
 
 }  // namespace salf

@@ -21,9 +21,7 @@ constexpr int kThreads = 256;
 // reset; read by salf_sync).  Walks are cut short only on pathological input, so the atomic is
 // off the hot path.
 __device__ uint32_t g_cut_rays;
-__device__ __forceinline__ void note_cut(bool whole) {
-  if (!whole) atomicAdd(&g_cut_rays, 1u);
-}
+__device__ __forceinline__ void note_cut() { atomicAdd(&g_cut_rays, 1u); }
 
 // The ray of this lane of wave `wave` (tiled: the wave's tile; else 64 consecutive rays): its
 // index and grid frame.  Returns false for lanes without a ray.
@@ -90,9 +88,10 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const int S = p.S;
   const double rS = 1.0 / S;
   const float t_min = p.t_min;
-  note_cut(traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
+  bool cut = false;
+  traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
     return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
-  }));
+  }, [&] { cut = true; });
   const salf_outputs& out = p.out;
   if (out.rgb) {
 #pragma unroll
@@ -103,6 +102,8 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   if (out.intensity) out.intensity[ray] = acc.I;
   if (out.t_end) out.t_end[ray] = acc.T;
   if (out.n_hits) out.n_hits[ray] = acc.n;
+  // Counted after the stores: the report stays out of the traversal loop's register budget.
+  if (cut) note_cut();
 }
 
 // At most 168 VGPRs, so that three waves fit each SIMD: the heavier variants (raw logits, colour
@@ -242,10 +243,10 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
         actor_ray(cp.slot[k], o, d, oa, da);
       }
       const RayFrame fr = make_frame(sv, oa, da, t0, t1);
-      note_cut(traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+      traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
         alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
         return alive;
-      }));
+      }, note_cut);
     }
     if (!alive) ray_done = true;
   }
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays 
   acc.C[0] = acc.C[1] = acc.C[2] = 0.0f;
   acc.D = acc.I = 0.0f;
   acc.n = 0;
-  note_cut(traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     if (n < max_hits) {
       ids[base + n] = h.voxel;
       t_in[base + n] = h.t_in;
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(SceneView s, salf_rays 
     ++n;
     if constexpr (FIELD >= 0) return shade_voxel<FIELD, false, false>(s, f, sh, h, S, rS, t_min, acc);
     return true;
-  }));
+  }, note_cut);
   counts[ray] = n;
 }
 
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   // degree-1 SH basis of the ray direction (paper field), as in the forward
   const float shb[4] = {kShC0, kShC1 * dir[0], kShC1 * dir[1], kShC1 * dir[2]};
-  note_cut(traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
     // activated corner values (stored ones when the scene keeps them, else from the logits); for
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       if (dst) unsafeAtomicAdd(dst, sum);
     }
     return ++count < n_stop;
-  }));
+  }, note_cut);
 }
 
 template <int FIELD>
