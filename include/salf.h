@@ -306,7 +306,20 @@ typedef struct {
   int32_t schedule;          /* tile schedule: SALF_SCHEDULE_NONE, _BUILD or _REUSE (see below)      */
   void* d_work;              /* schedule buffer (salf_render_work_size bytes, 256-byte aligned)      */
   size_t work_bytes;         /* its size; both ignored with SALF_SCHEDULE_NONE                      */
+  int32_t pieces;            /* lanes per ray: 0 or 1 = one; 2, 4 or 8 = see below                  */
+  int32_t reserved;          /* must be 0                                                           */
 } salf_render_opts;
+
+/* Rays in pieces (opts->pieces = P in {2, 4, 8}; salf_render and salf_render_static only, other
+ * entry points return UNSUPPORTED): P lanes share each ray.  Round by round, each lane walks the
+ * next of the ray's occupied root cells in turn and composites it from T = 1 (Eq. 3-4 within the
+ * cell); the P partial results are folded front to back into the ray (C += T C_j, D += T D_j,
+ * I += T I_j, T *= T_j).  Where the fold would take T below t_min inside a cell, that cell is
+ * composited again from the ray's state, so the ray stops after the same voxel as with one lane,
+ * up to the FP32 rounding of T; outputs equal the one-lane render's to FP32 rounding, not bit for
+ * bit.  The hits are those of the one-lane walk.  For launches with too few rays to fill the GPU
+ * (a LiDAR sweep: 2,048 waves of 64 rays against 256 CUs), whose time is that of their longest
+ * rays: P times the waves, each ray's cells walked side by side. */
 
 /* Tile schedules.  A render runs one wave per 64-ray tile.  A schedule estimates every tile's
  * cost by walking its centre ray through the root grid (for each occupied root cell, the length

@@ -55,7 +55,8 @@ class Rays(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("samples_per_voxel", C.c_int32), ("t_min", C.c_float), ("background", C.c_float * 3),
-                ("schedule", C.c_int32), ("d_work", C.c_void_p), ("work_bytes", C.c_size_t)]
+                ("schedule", C.c_int32), ("d_work", C.c_void_p), ("work_bytes", C.c_size_t),
+                ("pieces", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Outputs(C.Structure):

@@ -241,7 +241,7 @@ def generate_rays(sensor: dict, device="cuda") -> Dict[str, torch.Tensor]:
 
 
 def _opts(samples, t_min, background, work: Optional[torch.Tensor] = None,
-          mode: int = _lib.SCHEDULE_NONE) -> _lib.RenderOpts:
+          mode: int = _lib.SCHEDULE_NONE, pieces: int = 1) -> _lib.RenderOpts:
     op = _lib.RenderOpts()
     op.samples_per_voxel = int(samples)
     op.t_min = float(t_min)
@@ -249,6 +249,8 @@ def _opts(samples, t_min, background, work: Optional[torch.Tensor] = None,
     op.schedule = int(mode) if work is not None else _lib.SCHEDULE_NONE
     op.d_work = work.data_ptr() if work is not None else None
     op.work_bytes = work.numel() if work is not None else 0
+    op.pieces = int(pieces)
+    op.reserved = 0
     return op
 
 
@@ -310,13 +312,16 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
            d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
            outputs: Iterable[str] = ("rgb", "depth", "opacity"), t_near: float = 0.0, t_far: float = math.inf,
            out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0,
-           schedule=True) -> Dict[str, torch.Tensor]:
+           schedule=True, pieces: int = 1) -> Dict[str, torch.Tensor]:
     """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
     image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
     schedule: True builds a heaviest-tiles-first schedule in the call, a buffer from
     render_schedule reuses one, False keeps tile order, "static" builds it in the library's own
     per-device array (salf_render_static: no schedule memory is allocated; calls on one device
     must not overlap).  The outputs are the same bits in every case.
+    pieces: lanes per ray (1; or 2, 4, 8: each ray's occupied root cells are shared out among that
+    many lanes and their partial results folded front to back; the same hits, outputs equal to
+    the one-lane render's up to FP32 rounding).
     Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
     n_hits int32 [n])."""
     dev = scene.device
@@ -343,12 +348,12 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
         if schedule != "static":
             raise ValueError(f"unknown schedule {schedule!r}")
         call("salf_render_static", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-             C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background)), C.byref(ob),
-             _stream(dev))
+             C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, pieces=pieces)),
+             C.byref(ob), _stream(dev))
         return res
     work, mode = _schedule_args(schedule, sen, rays, dev)
     call("salf_render", scene.ctx.handle, scene.id, C.byref(sen) if sen is not None else None,
-         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work, mode)),
+         C.byref(rays) if rays is not None else None, C.byref(_opts(samples, t_min, background, work, mode, pieces)),
          C.byref(ob), _stream(dev))
     return res
 

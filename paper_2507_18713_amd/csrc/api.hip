@@ -118,6 +118,14 @@ salf_status salf::validate_opts(const salf_render_opts* o) {
   if (!(o->t_min >= 0.0f) || !(o->t_min <= 1.0f)) return set_error(SALF_ERR_INVALID_ARG, "t_min must be in [0, 1]");
   if (o->schedule < SALF_SCHEDULE_NONE || o->schedule > SALF_SCHEDULE_REUSE)
     return set_error(SALF_ERR_INVALID_ARG, "schedule must be SALF_SCHEDULE_NONE, _BUILD or _REUSE");
+  if (o->pieces != 0 && o->pieces != 1 && o->pieces != 2 && o->pieces != 4 && o->pieces != 8)
+    return set_error(SALF_ERR_INVALID_ARG, "pieces must be 0, 1, 2, 4 or 8");
+  if (o->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "reserved must be 0");
+  return SALF_OK;
+}
+
+salf_status salf::one_lane_per_ray(const salf_render_opts* o, const char* what) {
+  if (o && o->pieces > 1) return set_error(SALF_ERR_UNSUPPORTED, "%s walk each ray with one lane (pieces <= 1)", what);
   return SALF_OK;
 }
 
@@ -194,6 +202,7 @@ salf_status prepare_render(salf_context* ctx, int32_t scene_id, const salf_senso
   p->S = opts->samples_per_voxel;
   p->t_min = opts->t_min;
   for (int c = 0; c < 3; ++c) p->bg[c] = opts->background[c];
+  p->pieces = opts->pieces > 1 ? opts->pieces : 1;
   *field = sc.desc.field;
   return SALF_OK;
 }
@@ -372,6 +381,7 @@ salf_status salf_scene_create(salf_context* ctx, const salf_scene_desc* desc, in
   v.lmax = (const int32_t*)((char*)d_workspace + L.lmax_off);
   v.rbox = (const uint2*)((char*)d_workspace + L.rbox_off);
   sc.vbox = (const int4*)((char*)d_workspace + L.vbox_off);
+  v.cell = (const int4*)((char*)d_workspace + L.cell_off);
   v.boff = nullptr;
   v.cidx = nullptr;
   v.act_geo = v.act_rgb = v.act_int = nullptr;
@@ -450,7 +460,17 @@ salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t 
   Scene sc;
   salf_status st = check_index_args(ctx, scene_id, max_level, &sc);
   if (st) return st;
-  if (max_level == 0) return attach_index(ctx, scene_id, sc, nullptr, nullptr);
+  if (max_level == 0) {
+    // the traversal's root-cell records lose their index offsets, then the scene its index
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return set_error(SALF_ERR_DEVICE, "cannot select device %d", ctx->device);
+    SceneView v = sc.view;
+    v.boff = nullptr;
+    if ((st = check_hip(launch_pack_cells(v, sc.layout.n_root, (hipStream_t)stream), "cell records launch")) ||
+        (st = check_hip(hipStreamSynchronize((hipStream_t)stream), "cell records")))
+      return st;
+    return attach_index(ctx, scene_id, sc, nullptr, nullptr);
+  }
   if (!d_index || ((uintptr_t)d_index & 255u)) return set_error(SALF_ERR_INVALID_ARG, "index must be 256-byte aligned");
   std::vector<int32_t> boff;
   int64_t entries = 0;
@@ -466,6 +486,9 @@ salf_status salf_scene_build_index(salf_context* ctx, int32_t scene_id, int32_t 
   if ((st = check_hip(hipMemcpyAsync(d_boff, boff.data(), n_root * 4, hipMemcpyHostToDevice, s), "copy index offsets")))
     return st;
   if ((st = check_hip(launch_index_fill(sc.view, n_root, d_boff, d_entries, s), "index launch"))) return st;
+  SceneView v = sc.view;
+  v.boff = d_boff;
+  if ((st = check_hip(launch_pack_cells(v, n_root, s), "cell records launch"))) return st;
   if ((st = check_hip(hipStreamSynchronize(s), "index build"))) return st;
   return attach_index(ctx, scene_id, sc, d_boff, d_entries);
 }
@@ -625,7 +648,7 @@ salf_status salf_render_raster(salf_context* ctx, int32_t scene_id, const salf_s
   int field = 0;
   salf_status st = raster_setup(ctx, scene_id, sensor, &p, &field);
   if (st) return st;
-  if ((st = validate_opts(opts))) return st;
+  if ((st = validate_opts(opts)) || (st = one_lane_per_ray(opts, "splatting renders"))) return st;
   if (!out || !n_pairs) return set_error(SALF_ERR_INVALID_ARG, "outputs and n_pairs are required");
   if (out->rgb && !p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
   if (out->intensity && !p.scene.inten)
@@ -686,6 +709,7 @@ salf_status salf_render_multi(salf_context* ctx, int32_t n_items, const salf_ren
     salf_render_opts o = it.opts;
     o.schedule = SALF_SCHEDULE_NONE;
     int field = 0;
+    if ((st = one_lane_per_ray(&o, "multi-sensor launches"))) return st;
     if ((st = prepare_render(ctx, it.scene_id, it.sensor, nullptr, &o, &b.p, &field))) return st;
     if (field != SALF_FIELD_CORNER) return set_error(SALF_ERR_UNSUPPORTED, "item %d: multi-sensor launches render corner-field scenes", i);
     if (it.out.rgb && !b.p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "item %d: colour from a scene without colour", i);
@@ -745,8 +769,8 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
   CompositeParams cp;
   memset(&cp, 0, sizeof(cp));
   int field = 0;
-  salf_status st = prepare_render(ctx, static_scene_id, sensor, rays, opts, &cp.base, &field);
-  if (st) return st;
+  salf_status st = one_lane_per_ray(opts, "renders with actors");
+  if (st || (st = prepare_render(ctx, static_scene_id, sensor, rays, opts, &cp.base, &field))) return st;
   if (!out) return set_error(SALF_ERR_INVALID_ARG, "outputs is NULL");
   if (n_actors < 0 || n_actors > SALF_MAX_ACTORS || (n_actors > 0 && !actors))
     return set_error(SALF_ERR_INVALID_ARG, "n_actors %d outside [0, %d] or actors NULL", n_actors, SALF_MAX_ACTORS);
@@ -815,8 +839,8 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
                                  float* d_dgeo, float* d_drgb, float* d_dint, void* stream) {
   BackwardParams b;
   int field = 0;
-  salf_status st = prepare_render(ctx, scene_id, sensor, rays, opts, &b.fwd, &field);
-  if (st) return st;
+  salf_status st = one_lane_per_ray(opts, "backward passes");
+  if (st || (st = prepare_render(ctx, scene_id, sensor, rays, opts, &b.fwd, &field))) return st;
   if (!saved || !grads) return set_error(SALF_ERR_INVALID_ARG, "saved outputs and gradients are required");
   if (!saved->t_end || !saved->n_hits) return set_error(SALF_ERR_INVALID_ARG, "saved t_end and n_hits are required");
   if (grads->d_rgb && (!saved->rgb || !b.fwd.scene.rgb))

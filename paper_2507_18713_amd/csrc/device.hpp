@@ -41,6 +41,8 @@ struct SceneView {
   const int32_t* boff;   // [Dz][Dy][Dx] first entry of each root cell's dense leaf index, or -1;
                          // null: no index
   const uint32_t* cidx;  // dense leaf indexes (see kIdx* below)
+  const int4* cell;      // [Dz][Dy][Dx] what a root step reads, in one 16-byte record: x the code,
+                         // y boff (-1 without an index), z rbox.x | skip << 24, w rbox.y | lmax << 24
   const float* act_geo;  // activated corner values (pre-activated corner scenes), same layouts as
   const float* act_rgb;  // geo / rgb / inten; null otherwise
   const float* act_int;
@@ -341,6 +343,97 @@ __device__ __forceinline__ bool index_walk(const SceneView& s, const RayFrame& f
   return true;
 }
 
+// The leaf loop of a root cell without a dense leaf index, from tc to cell_end: each pass descends
+// from the cell's node (code) to the leaf holding tc, reports the leaf if it holds a voxel, moves tc
+// to the leaf's exit crossing and pops the nodes tc has left.  lo: the cell's min corner (changed);
+// stk: the lane's node stack.  False if visit asked to stop.
+template <typename Visit>
+__device__ __forceinline__ bool octree_walk(const SceneView& s, const RayFrame& f, int32_t lo[3], int32_t code,
+                                            float tc, float cell_end, int32_t* stk, int stride, int& budget, Hit& h,
+                                            Visit&& visit) {
+  const int K = s.K;
+  int depth = 0;
+  int32_t size = 1 << K;
+  stk[0] = code;
+  const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
+  int4 c0 = np[0], c1 = np[1];
+  while (tc < cell_end && budget-- > 0) {
+    // (1) descend to the leaf holding tc
+    int32_t clo[3], half, child;
+    for (;;) {
+      half = size >> 1;
+      int c8 = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int32_t mid = lo[a] + half;
+        bool upper;
+        if (f.par & (1 << a)) {
+          upper = f.og[a] >= (float)mid;
+        } else {
+          const bool past = plane_t((float)mid, f.og[a], f.inv[a]) <= tc;
+          upper = (f.inv[a] > 0.0f) ? past : !past;
+        }
+        clo[a] = upper ? mid : lo[a];
+        c8 |= upper ? (1 << a) : 0;
+      }
+      child = pick8(c0, c1, c8);
+      // internal children exist only above the finest level; deeper would be malformed: empty
+      if (child < 0 || depth + 1 >= K) break;
+      // an internal node: enter it where the ray meets its voxels' bounds, or pass it like an
+      // empty leaf if they lie behind tc or off the ray
+      np = reinterpret_cast<const int4*>(s.nodes + (int64_t)child * 8);
+      const int4 n0 = np[0], n1 = np[1];
+      float c_in, c_out;
+      const bool hit = node_bounds(f, clo, s.nbox[child], c_in, c_out);
+      const float c_tc = fmaxf(tc, c_in);
+      if (!hit || !(c_tc < c_out)) {
+        child = kEmpty;
+        break;
+      }
+      tc = c_tc;
+      ++depth;
+      stk[depth * stride] = child;
+      size = half;
+      lo[0] = clo[0];
+      lo[1] = clo[1];
+      lo[2] = clo[2];
+      c0 = n0;
+      c1 = n1;
+    }
+    // (2) the leaf [clo, clo + half): report a voxel
+    const float to = box_exit(f, clo, half);
+    if (is_leaf_code(child)) {
+      h.voxel = leaf_voxel(child);
+      h.lo[0] = clo[0];
+      h.lo[1] = clo[1];
+      h.lo[2] = clo[2];
+      h.size = half;
+      h.t_in = tc;
+      h.t_out = to;
+      if (!visit(h)) return false;
+    }
+    // (3) advance and leave every node that no longer holds tc
+    if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
+    tc = to;
+    if (!(tc < cell_end)) break;
+    bool popped = false;
+    while (depth > 0 && !(tc < box_exit(f, lo, size))) {
+      --depth;
+      size <<= 1;
+      lo[0] &= ~(size - 1);
+      lo[1] &= ~(size - 1);
+      lo[2] &= ~(size - 1);
+      popped = true;
+    }
+    if (popped) {
+      np = reinterpret_cast<const int4*>(s.nodes + (int64_t)stk[depth * stride] * 8);
+      c0 = np[0];
+      c1 = np[1];
+    }
+  }
+  return true;
+}
+
 // Front-to-back walk over the voxels a ray hits: calls visit(hit) for each, in increasing t_in,
 // until visit returns false.  Each voxel is reported exactly once with the rule's interval.
 //
@@ -382,11 +475,12 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
   while (budget-- > 0) {
     const float cell_exit = fminf(fminf(ax.nxt, ay.nxt), fminf(az.nxt, t_exit));
     const int64_t lin = ((int64_t)az.k * s.dims[1] + ay.k) * s.dims[0] + ax.k;
-    // the cell's code, voxel bounds, skip distance and index offset, read together
-    const int32_t code = s.root[lin];
-    const uint2 rb = s.rbox[lin];
-    const int dskip = s.skip != nullptr ? s.skip[lin] : 0;
-    const int32_t bo = s.boff != nullptr ? s.boff[lin] : -1;
+    // the cell's code, index offset, voxel bounds, skip distance and finest level: one record
+    const int4 rec = s.cell[lin];
+    const int32_t code = rec.x;
+    const int32_t bo = rec.y;
+    const uint2 rb = make_uint2((uint32_t)rec.z, (uint32_t)rec.w);  // node_bounds reads the low 3 bytes
+    const int dskip = (int)((uint32_t)rec.z >> 24);
     float t_next = cell_exit;
     if (code >= 0) {
       // octree of this root cell, entered where the ray meets the bounds of its voxels
@@ -397,90 +491,11 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
       const float cell_end = fminf(cell_exit, b_out);
       if (!meets) tc = cell_end;
       if (bo >= 0) {
-        if (!index_walk(s, f, lo, s.lmax[lin], s.cidx + bo, tc, cell_end, budget, h, visit)) return;
-        if (budget <= 0) break;  // the cell's walk used up the budget: the ray is cut short
-      } else {
-      int depth = 0;
-      int32_t size = N0;
-      stk[0] = code;
-      const int4* np = reinterpret_cast<const int4*>(s.nodes + (int64_t)code * 8);
-      int4 c0 = np[0], c1 = np[1];
-      while (tc < cell_end && budget-- > 0) {
-        // (1) descend to the leaf holding tc
-        int32_t clo[3], half, child;
-        for (;;) {
-          half = size >> 1;
-          int c8 = 0;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int32_t mid = lo[a] + half;
-            bool upper;
-            if (f.par & (1 << a)) {
-              upper = f.og[a] >= (float)mid;
-            } else {
-              const bool past = plane_t((float)mid, f.og[a], f.inv[a]) <= tc;
-              upper = (f.inv[a] > 0.0f) ? past : !past;
-            }
-            clo[a] = upper ? mid : lo[a];
-            c8 |= upper ? (1 << a) : 0;
-          }
-          child = pick8(c0, c1, c8);
-          // internal children exist only above the finest level; deeper would be malformed: empty
-          if (child < 0 || depth + 1 >= K) break;
-          // an internal node: enter it where the ray meets its voxels' bounds, or pass it like an
-          // empty leaf if they lie behind tc or off the ray
-          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)child * 8);
-          const int4 n0 = np[0], n1 = np[1];
-          float c_in, c_out;
-          const bool hit = node_bounds(f, clo, s.nbox[child], c_in, c_out);
-          const float c_tc = fmaxf(tc, c_in);
-          if (!hit || !(c_tc < c_out)) {
-            child = kEmpty;
-            break;
-          }
-          tc = c_tc;
-          ++depth;
-          stk[depth * stride] = child;
-          size = half;
-          lo[0] = clo[0];
-          lo[1] = clo[1];
-          lo[2] = clo[2];
-          c0 = n0;
-          c1 = n1;
-        }
-        // (2) the leaf [clo, clo + half): report a voxel
-        const float to = box_exit(f, clo, half);
-        if (is_leaf_code(child)) {
-          h.voxel = leaf_voxel(child);
-          h.lo[0] = clo[0];
-          h.lo[1] = clo[1];
-          h.lo[2] = clo[2];
-          h.size = half;
-          h.t_in = tc;
-          h.t_out = to;
-          if (!visit(h)) return;
-        }
-        // (3) advance and leave every node that no longer holds tc
-        if (!(to > tc)) break;  // cannot happen under the rule; guards against a stall
-        tc = to;
-        if (!(tc < cell_end)) break;
-        bool popped = false;
-        while (depth > 0 && !(tc < box_exit(f, lo, size))) {
-          --depth;
-          size <<= 1;
-          lo[0] &= ~(size - 1);
-          lo[1] &= ~(size - 1);
-          lo[2] &= ~(size - 1);
-          popped = true;
-        }
-        if (popped) {
-          np = reinterpret_cast<const int4*>(s.nodes + (int64_t)stk[depth * stride] * 8);
-          c0 = np[0];
-          c1 = np[1];
-        }
+        if (!index_walk(s, f, lo, (int)((uint32_t)rec.w >> 24), s.cidx + bo, tc, cell_end, budget, h, visit)) return;
+      } else if (!octree_walk(s, f, lo, code, tc, cell_end, stk, stride, budget, h, visit)) {
+        return;
       }
-      if (budget <= 0) break;
-      }
+      if (budget <= 0) break;  // the cell's walk used up the budget: the ray is cut short
     } else if (is_leaf_code(code)) {
       // a level-0 voxel fills the root cell: it holds t, so its interval is [t, cell_exit]
       h.voxel = leaf_voxel(code);
@@ -504,6 +519,116 @@ __device__ inline void traverse(const SceneView& s, const RayFrame& f, int32_t* 
   cut();  // the step budget ran out
 }
 
+
+// ---- a ray's root cells shared out among several lanes
+// A root cell holding voxels, as the root walk meets it: what its leaf loop needs.
+struct CellJob {
+  int32_t lo[3];       // the cell's min corner (finest cells)
+  int32_t code;        // its node (>= 0), or the leaf code of a voxel that fills it
+  int32_t bo, lmax;    // its dense leaf index (first entry, or -1) and finest voxel level
+  float tc, cell_end;  // the leaf loop's range (a filling voxel: its interval)
+};
+
+// Root-walk state of a ray between occupied cells: t at the current cell, where the ray leaves
+// the grid, and the per-axis cell indices.  The walk is over once t reaches t_exit.
+struct RootWalk {
+  float t, t_exit;
+  RootAxis ax, ay, az;
+};
+
+// Start the root walk where the ray enters the grid; false if it misses the grid.
+__device__ __forceinline__ bool root_walk_begin(const SceneView& s, const RayFrame& f, RootWalk& w) {
+  if (!f.valid) return false;
+  const int K = s.K;
+  const int32_t glo[3] = {0, 0, 0};
+  const int32_t ghi[3] = {s.dims[0] << K, s.dims[1] << K, s.dims[2] << K};
+  if (!box_interval(f, glo, ghi, w.t, w.t_exit) || !(w.t < w.t_exit)) return false;
+  root_axis_init<0>(f, s, w.t, w.ax);
+  root_axis_init<1>(f, s, w.t, w.ay);
+  root_axis_init<2>(f, s, w.t, w.az);
+  return true;
+}
+
+// Move the walk to t_next (the current cell's exit, or the exit of an empty cube around it).
+__device__ __forceinline__ void root_walk_step(const SceneView& s, const RayFrame& f, RootWalk& w, float t_next) {
+  if (!(t_next < w.t_exit)) {
+    w.t = w.t_exit;
+    return;
+  }
+  w.t = t_next;
+  if (!root_axis_advance<0>(f, s, w.t, w.ax) || !root_axis_advance<1>(f, s, w.t, w.ay) ||
+      !root_axis_advance<2>(f, s, w.t, w.az))
+    w.t = w.t_exit;
+}
+
+// Pass `skip` occupied root cells, then describe the next one in job and leave the walk just past
+// it.  Returns 1 with a job, 0 if the ray leaves the grid first, -1 if the step budget runs out.
+// The steps, crossings and cell ranges are those of traverse, so every lane that walks the same
+// ray meets the same occupied cells in the same order and the leaf loops find the same hits.
+__device__ __forceinline__ int root_walk_next(const SceneView& s, const RayFrame& f, RootWalk& w, int skip,
+                                              int& budget, CellJob& job) {
+  const int K = s.K;
+  if (!(w.t < w.t_exit)) return 0;
+  while (budget-- > 0) {
+    const float cell_exit = fminf(fminf(w.ax.nxt, w.ay.nxt), fminf(w.az.nxt, w.t_exit));
+    const int64_t lin = ((int64_t)w.az.k * s.dims[1] + w.ay.k) * s.dims[0] + w.ax.k;
+    const int4 rec = s.cell[lin];
+    const int32_t code = rec.x;
+    float t_next = cell_exit;
+    if (code >= 0 || is_leaf_code(code)) {
+      if (skip == 0) {
+        job.lo[0] = w.ax.k << K;
+        job.lo[1] = w.ay.k << K;
+        job.lo[2] = w.az.k << K;
+        job.code = code;
+        job.bo = -1;
+        job.lmax = 0;
+        job.tc = w.t;
+        job.cell_end = cell_exit;
+        if (code >= 0) {
+          float b_in, b_out;
+          const bool meets = node_bounds(f, job.lo, make_uint2((uint32_t)rec.z, (uint32_t)rec.w), b_in, b_out);
+          job.cell_end = fminf(cell_exit, b_out);
+          job.tc = meets ? fmaxf(w.t, b_in) : job.cell_end;
+          job.bo = rec.y;
+          if (job.bo >= 0) job.lmax = (int32_t)((uint32_t)rec.w >> 24);
+        }
+        root_walk_step(s, f, w, cell_exit);
+        return 1;
+      }
+      --skip;
+    } else {
+      const int dskip = (int)((uint32_t)rec.z >> 24);
+      if (dskip > 1)
+        t_next = fminf(fminf(cube_exit<0>(f, s, w.ax, dskip), cube_exit<1>(f, s, w.ay, dskip)),
+                       fminf(cube_exit<2>(f, s, w.az, dskip), w.t_exit));
+    }
+    root_walk_step(s, f, w, t_next);
+    if (!(w.t < w.t_exit)) return 0;
+  }
+  return -1;
+}
+
+// The leaf loop of one job: visit(hit) for each voxel of the cell the ray hits, in order, as
+// traverse reports them.  False if visit asked to stop.
+template <typename Visit>
+__device__ __forceinline__ bool walk_cell(const SceneView& s, const RayFrame& f, const CellJob& job, int32_t* stk,
+                                          int stride, int& budget, Hit& h, Visit&& visit) {
+  if (is_leaf_code(job.code)) {
+    h.voxel = leaf_voxel(job.code);
+    h.lo[0] = job.lo[0];
+    h.lo[1] = job.lo[1];
+    h.lo[2] = job.lo[2];
+    h.size = 1 << s.K;
+    h.t_in = job.tc;
+    h.t_out = job.cell_end;
+    return visit(h);
+  }
+  if (job.bo >= 0)
+    return index_walk(s, f, job.lo, job.lmax, s.cidx + job.bo, job.tc, job.cell_end, budget, h, visit);
+  int32_t lo[3] = {job.lo[0], job.lo[1], job.lo[2]};
+  return octree_walk(s, f, lo, job.code, job.tc, job.cell_end, stk, stride, budget, h, visit);
+}
 
 // Estimated number of voxels a ray crosses, from the root grid alone (used to schedule tiles):
 // for every occupied root cell on the ray, the length inside the bounds of the cell's voxels

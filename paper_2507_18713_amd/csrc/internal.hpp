@@ -28,6 +28,7 @@ struct SceneLayout {
   size_t lmax_off;   // finest voxel level per root cell
   size_t rbox_off;   // bounds of each root cell's voxels (uint2 per cell, zero for cells without a node)
   size_t vbox_off;   // each voxel's finest-cell box (int4: min corner, edge), for splatting
+  size_t cell_off;   // the traversal's packed root-cell records (int4 per root cell)
   size_t act_geo_off, act_rgb_off, act_int_off;  // pre-activated scenes only (else 0)
   size_t total;
 };
@@ -55,6 +56,9 @@ hipError_t launch_refine(const SceneView& v, const salf_scene_desc& d, int64_t n
                          int64_t* total, hipStream_t stream);
 
 // Dense leaf indexes of a built scene: boff[cell] is the first entry of the cell's index or -1.
+// Pack the traversal's root-cell records of v (v.cell) from its root codes, voxel bounds, skip
+// distances, finest levels and dense-index offsets (v.boff, or none).
+hipError_t launch_pack_cells(const SceneView& v, int64_t n_root, hipStream_t stream);
 hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
                              hipStream_t stream);
 
@@ -79,6 +83,7 @@ struct RenderParams {
   int32_t tiles_x, tiles_y;
   int32_t tw_log2;           // tile width 2^tw_log2, height 64 >> tw_log2
   const int32_t* sched;      // optional tile schedule (header + order, see launch_tile_schedule)
+  int32_t pieces;            // lanes per ray (1, 2, 4 or 8): > 1 shares each ray's root cells out
 };
 
 // int32 entries of the schedule buffer's header
@@ -236,4 +241,6 @@ salf_status scene_snapshot(salf_context* ctx, int32_t scene_id, Scene* out);
 // Validation shared by the entry points.
 salf_status validate_sensor(const salf_sensor* s);
 salf_status validate_opts(const salf_render_opts* o);
+// UNSUPPORTED when o asks for several lanes per ray (entry points whose kernels walk a ray with one lane).
+salf_status one_lane_per_ray(const salf_render_opts* o, const char* what);
 }  // namespace salf

@@ -72,8 +72,12 @@ __device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t
 
 // Render the rays of one wave (tile `wave` of p) and store their outputs.  stk: this lane's node
 // stack (stride kThreads).  Shared by the single-request kernel and the batched kernel, so a ray
-// renders to the same bits alone or in a batch.
-template <int FIELD, bool RGB, bool INT>
+// renders to the same bits alone or in a batch.  p_is_kernarg: p is the kernel's only argument;
+// the output pointers and background are then read again from the argument block after the walk
+// (an opaque copy of its address keeps the compiler from loading them up front), rather than held
+// in scalar registers through it: those are short in the walk, and every extra value there is
+// spilled and reloaded inside its loops.
+template <int FIELD, bool RGB, bool INT, bool p_is_kernarg = false>
 __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk) {
   int64_t ray;
   float d[3];
@@ -92,10 +96,15 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
     return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
   }, [&] { cut = true; });
-  const salf_outputs& out = p.out;
+  const RenderParams* q = &p;
+  if (p_is_kernarg) {
+    q = (const RenderParams*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(q));
+  }
+  const salf_outputs& out = q->out;
   if (out.rgb) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = fmaf(acc.T, p.bg[ch], acc.C[ch]);
+    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = fmaf(acc.T, q->bg[ch], acc.C[ch]);
   }
   if (out.depth) out.depth[ray] = acc.D;
   if (out.opacity) out.opacity[ray] = 1.0f - acc.T;
@@ -115,7 +124,127 @@ template <int FIELD, bool RGB, bool INT>
 __global__ __launch_bounds__(kThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
-  render_wave<FIELD, RGB, INT>(p, scheduled_tile(p, w), stk + threadIdx.x);
+  render_wave<FIELD, RGB, INT, true>(p, scheduled_tile(p, w), stk + threadIdx.x);
+}
+
+// ---- one ray in pieces
+// P consecutive lanes (P = 2, 4 or 8) share one ray: round by round, lane g walks the ray's
+// (rP + g)-th occupied root cell and composites it from T = 1; the P partial results are then
+// folded front to back (C += T C_j, D += T D_j, I += T I_j, T *= T_j) into the ray's state, which
+// every lane of the group holds.  Where the fold would leave T below t_min inside a cell, that
+// cell's lane walks it again from the ray's state with the stopping rule, so the ray stops after
+// the voxel a one-lane walk stops after (up to the rounding of T).  For launches with too few rays
+// to fill the GPU: a long ray's cells are walked side by side instead of one after another.
+template <int FIELD, bool RGB, bool INT>
+__global__ __launch_bounds__(kThreads) void render_split_kernel(RenderParams p) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  const int P = p.pieces;
+  const int lane = threadIdx.x & 63;
+  const int g = lane & (P - 1);
+  const int base = lane - g;
+  const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  int64_t ray;
+  float d[3];
+  RayFrame f;
+  // split wave w covers lanes (w % P) * 64 / P ... of the one-lane layout's wave w / P
+  if (!lane_ray(p, scheduled_tile(p, w / P), (int)(w % P) * (64 / P) + lane / P, ray, d, f)) return;
+  const SceneView& s = p.scene;
+  const float sh[4] = {kShC0, kShC1 * d[0], kShC1 * d[1], kShC1 * d[2]};
+  const int S = p.S;
+  const double rS = 1.0 / S;
+  const float t_min = p.t_min;
+  int32_t* my_stk = stk + threadIdx.x;
+  Accum acc;
+  acc.T = 1.0f;
+  acc.C[0] = acc.C[1] = acc.C[2] = 0.0f;
+  acc.D = acc.I = 0.0f;
+  acc.n = 0;
+  int budget = s.step_budget;
+  RootWalk rw;
+  bool walking = root_walk_begin(s, f, rw);
+  bool cut = false;
+  int skip = g;
+  for (;;) {
+    CellJob job;
+    bool has = false;
+    if (walking) {
+      const int r = root_walk_next(s, f, rw, skip, budget, job);
+      has = r > 0;
+      walking = r > 0;
+      cut = cut || r < 0;
+    }
+    skip = P - 1;
+    Accum part;
+    part.T = 1.0f;
+    part.C[0] = part.C[1] = part.C[2] = 0.0f;
+    part.D = part.I = 0.0f;
+    part.n = 0;
+    if (has) {
+      Hit h;
+      // a partial may stop once its own T < t_min: the ray's T (no larger) is below it too
+      walk_cell(s, f, job, my_stk, kThreads, budget, h, [&](const Hit& x) -> bool {
+        return shade_voxel<FIELD, RGB, INT>(s, f, sh, x, S, rS, t_min, part);
+      });
+      if (budget <= 0) {
+        cut = true;
+        walking = false;
+      }
+    }
+    // fold the group's partials in cell order (every lane of the group computes the same)
+    bool any = false, stop = false;
+    for (int j = 0; j < P; ++j) {
+      const int src = base + j;
+      if (__shfl((int)has, src) == 0) continue;
+      any = true;
+      const float pT = __shfl(part.T, src);
+      if (acc.T * pT < t_min) {
+        // the ray stops inside cell j: its lane walks the cell again from the ray's state
+        if (g == j) {
+          Hit h;
+          int again = s.step_budget;
+          walk_cell(s, f, job, my_stk, kThreads, again, h, [&](const Hit& x) -> bool {
+            return shade_voxel<FIELD, RGB, INT>(s, f, sh, x, S, rS, t_min, acc);
+          });
+        }
+        acc.T = __shfl(acc.T, src);
+        if (RGB) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) acc.C[ch] = __shfl(acc.C[ch], src);
+        }
+        acc.D = __shfl(acc.D, src);
+        if (INT) acc.I = __shfl(acc.I, src);
+        acc.n = __shfl(acc.n, src);
+        if (acc.T < t_min) {
+          stop = true;
+          break;
+        }
+        continue;
+      }
+      if (RGB) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) acc.C[ch] = fmaf(acc.T, __shfl(part.C[ch], src), acc.C[ch]);
+      }
+      acc.D = fmaf(acc.T, __shfl(part.D, src), acc.D);
+      if (INT) acc.I = fmaf(acc.T, __shfl(part.I, src), acc.I);
+      acc.n += __shfl(part.n, src);
+      acc.T *= pT;
+    }
+    if (stop || !any) break;
+  }
+  bool cut_any = false;
+  for (int j = 0; j < P; ++j) cut_any = cut_any || __shfl((int)cut, base + j) != 0;
+  if (g != 0) return;
+  const salf_outputs& out = p.out;
+  if (out.rgb) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) out.rgb[ray * 3 + ch] = fmaf(acc.T, p.bg[ch], acc.C[ch]);
+  }
+  if (out.depth) out.depth[ray] = acc.D;
+  if (out.opacity) out.opacity[ray] = 1.0f - acc.T;
+  if (out.intensity) out.intensity[ray] = acc.I;
+  if (out.t_end) out.t_end[ray] = acc.T;
+  if (out.n_hits) out.n_hits[ray] = acc.n;
+  if (cut_any) note_cut();
 }
 
 // ---- a static scene with dynamic actors (merged traversal)
@@ -732,6 +861,14 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
 template <int FIELD>
 hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stream) {
   const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
+  if (p.pieces > 1) {
+    blocks *= (unsigned)p.pieces;
+    if (rgb && in) render_split_kernel<FIELD, true, true><<<blocks, kThreads, 0, stream>>>(p);
+    else if (rgb) render_split_kernel<FIELD, true, false><<<blocks, kThreads, 0, stream>>>(p);
+    else if (in) render_split_kernel<FIELD, false, true><<<blocks, kThreads, 0, stream>>>(p);
+    else render_split_kernel<FIELD, false, false><<<blocks, kThreads, 0, stream>>>(p);
+    return hipGetLastError();
+  }
   if (rgb && in) render_kernel<FIELD, true, true><<<blocks, kThreads, 0, stream>>>(p);
   else if (rgb) render_kernel<FIELD, true, false><<<blocks, kThreads, 0, stream>>>(p);
   else if (in) render_kernel<FIELD, false, true><<<blocks, kThreads, 0, stream>>>(p);

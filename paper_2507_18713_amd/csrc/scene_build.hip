@@ -413,6 +413,8 @@ bool scene_layout(const salf_scene_desc& d, int64_t n, SceneLayout* L) {
     L->act_int_off = off;
     off = up(off + (size_t)n * 8 * 4);
   }
+  L->cell_off = off;
+  off = up(off + (size_t)n_root * 16);
   L->total = off;
   return true;
 }
@@ -658,6 +660,26 @@ hipError_t launch_refine(const SceneView& v, const salf_scene_desc& d, int64_t n
   return hipStreamSynchronize(stream);
 }
 
+namespace {
+__global__ void pack_cells_kernel(const int32_t* root, const uint2* rbox, const uint8_t* skip, const int32_t* lmax,
+                                  const int32_t* boff, int64_t n_root, int4* cell) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_root) return;
+  const uint2 b = rbox[i];
+  const uint32_t sk = skip != nullptr ? (uint32_t)skip[i] : 0u;
+  const uint32_t lm = (uint32_t)lmax[i] & 255u;
+  cell[i] = make_int4(root[i], boff != nullptr ? boff[i] : -1, (int32_t)((b.x & 0xffffffu) | (sk << 24)),
+                      (int32_t)((b.y & 0xffffffu) | (lm << 24)));
+}
+}  // namespace
+
+hipError_t launch_pack_cells(const SceneView& v, int64_t n_root, hipStream_t stream) {
+  if (n_root <= 0) return hipSuccess;
+  pack_cells_kernel<<<blocks_for(n_root, 256), 256, 0, stream>>>(v.root, v.rbox, v.skip, v.lmax, v.boff, n_root,
+                                                                  const_cast<int4*>(v.cell));
+  return hipGetLastError();
+}
+
 hipError_t launch_index_fill(const SceneView& v, int64_t n_root, const int32_t* boff, uint32_t* entries,
                              hipStream_t stream) {
   for (int64_t c0 = 0; c0 < n_root; c0 += (int64_t)1 << 30) {
@@ -722,6 +744,9 @@ hipError_t launch_scene_build(const salf_scene_desc& d, int64_t n, const int32_t
                                                                                                   a.cnt);
   // (a voxel outside [0, K] fails the build before its box is read)
   if (n > 0) vbox_kernel<<<blocks_for(n, T), T, 0, stream>>>(voxels, n, a.K, (int4*)(base + L.vbox_off));
+  pack_cells_kernel<<<blocks_for(L.n_root, T), T, 0, stream>>>(a.root, (const uint2*)(base + L.rbox_off),
+                                                               (const uint8_t*)(base + L.skip_off), a.lmax, nullptr,
+                                                               L.n_root, (int4*)(base + L.cell_off));
   return hipGetLastError();
 }
 

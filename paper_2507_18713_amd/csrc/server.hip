@@ -328,7 +328,7 @@ salf_status salf_server_submit(salf_server* server, int32_t scene_id, const salf
   if (!server || !ticket) return set_error(SALF_ERR_INVALID_ARG, "NULL argument");
   salf_status st = validate_sensor(sensor);
   if (st) return st;
-  if ((st = validate_opts(opts))) return st;
+  if ((st = validate_opts(opts)) || (st = one_lane_per_ray(opts, "served requests"))) return st;
   if (outputs == 0 || (outputs & ~15u)) return set_error(SALF_ERR_INVALID_ARG, "bad output mask %u", outputs);
   Scene sc;
   if ((st = scene_snapshot(server->ctx, scene_id, &sc))) return st;

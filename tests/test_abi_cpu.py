@@ -47,7 +47,7 @@ int main(void) {
   printf("SceneStats %zu %zu\n", sizeof(salf_scene_stats), offsetof(salf_scene_stats, workspace_bytes));
   printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
   printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
-  printf("RenderOpts %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, schedule), offsetof(salf_render_opts, work_bytes));
+  printf("RenderOpts %zu %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, schedule), offsetof(salf_render_opts, work_bytes), offsetof(salf_render_opts, pieces));
   printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
   printf("ServerOpts %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight));
@@ -68,7 +68,8 @@ int main(void) {
         "SceneStats": [C.sizeof(S.SceneStats), S.SceneStats.workspace_bytes.offset],
         "Sensor": [C.sizeof(S.Sensor), S.Sensor.R0.offset, S.Sensor.t_far.offset],
         "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
-        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.schedule.offset, S.RenderOpts.work_bytes.offset],
+        "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.schedule.offset, S.RenderOpts.work_bytes.offset,
+                       S.RenderOpts.pieces.offset],
         "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
         "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset],
@@ -97,10 +98,10 @@ def test_workspace_size_host_logic(L):
     assert n.value > small
     # a K = 0 scene needs no nodes: the root grid and the finest-level grid (4 B per cell each),
     # the root-bounds grid (8 B per cell), the skip-distance grid and its two build-time
-    # temporaries (1 B per cell each), each voxel's box (16 B per voxel), a minimal hash table and
-    # the counters
+    # temporaries (1 B per cell each), the traversal's packed cell records (16 B per cell), each
+    # voxel's box (16 B per voxel), a minimal hash table and the counters
     assert lib.salf_scene_workspace_size(C.byref(_desc(L, dims=(32, 32, 32), K=0)), 4096, C.byref(n)) == 0
-    assert 32 ** 3 * 19 + 4096 * 16 <= n.value < 32 ** 3 * 19 + 4096 * 16 + 64 * 1024
+    assert 32 ** 3 * 35 + 4096 * 16 <= n.value < 32 ** 3 * 35 + 4096 * 16 + 64 * 1024
     # invalid descriptions
     for bad in (_desc(L, K=9), _desc(L, s0=0.0), _desc(L, s0=math.nan), _desc(L, dims=(0, 4, 4)),
                 _desc(L, dims=(1 << 17, 4, 4), K=4), _desc(L, field=7)):

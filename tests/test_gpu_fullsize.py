@@ -53,11 +53,13 @@ def pool():
     p.close()
 
 
-def _pooled_parity(salf, scenes, pool, o, d, width, outs, seed):
+def _pooled_parity(salf, scenes, pool, o, d, width, outs, seed, pieces=(1,)):
     """Sampled rays of a frame against the pooled oracle: hit lists bit for bit, outputs of every
-    scene variant (raw logits, pre-activated) to tolerance."""
+    scene variant (raw logits, pre-activated) rendered with every lane count per ray to tolerance."""
     rng = np.random.default_rng(seed)
-    full = [salf.render(sc, o=to_dev(o), d=to_dev(d), image_width=width, outputs=outs) for sc in scenes]
+    combos = [(i, pc) for i in range(len(scenes)) for pc in pieces]
+    full = [salf.render(scenes[i], o=to_dev(o), d=to_dev(d), image_width=width, outputs=outs, pieces=pc)
+            for i, pc in combos]
     nh = full[0]["n_hits"].cpu().numpy()
     heavy = np.argsort(-nh, kind="stable")[:N_HEAVY]
     idx = np.unique(np.concatenate([rng.choice(o.shape[0], N_SAMPLE, replace=False), heavy]))
@@ -77,7 +79,20 @@ def _pooled_parity(salf, scenes, pool, o, d, width, outs, seed):
         check_outputs(got, ref, idx=idx, keys=[k for k in outs if k != "n_hits"])
     # the pre-activated scene composites the same voxels; n_hits may differ only where FP32
     # rounding of the activation moves T across t_min, which the oracle's n_hits pins for the raw one
-    assert np.array_equal(full[0]["n_hits"].cpu().numpy()[idx], ref["n_hits"])
+    for (i, pc), got in zip(combos, full):
+        if i == 0:
+            assert np.array_equal(got["n_hits"].cpu().numpy()[idx], ref["n_hits"]), pc
+    # in pieces, every ray of the frame against the one-lane render: the same hit counts, outputs
+    # equal to FP32 rounding
+    for (i, pc), got in zip(combos, full):
+        one = full[combos.index((i, 1))] if (i, 1) in combos else None
+        if pc == 1 or one is None:
+            continue
+        assert torch.equal(got["n_hits"], one["n_hits"]), (i, pc)
+        for k in outs:
+            if k != "n_hits":
+                err = float(torch.max(torch.abs(got[k] - one[k])))
+                assert err <= (1e-3 if k == "depth" else 2e-5), (i, pc, k, err)
     return full[0], int(ref["n_hits"].sum())
 
 
@@ -127,7 +142,7 @@ def test_lidar_sweep(salf, c1, c1_preactivated, pool):
     lid = synth.config2_lidar()
     o, d, _ = oracle_rays(lid)
     outs = ("depth", "intensity", "opacity", "t_end", "n_hits")
-    got, n_hits = _pooled_parity(salf, (scene, c1_preactivated), pool, o, d, 2048, outs, seed=72)
+    got, n_hits = _pooled_parity(salf, (scene, c1_preactivated), pool, o, d, 2048, outs, seed=72, pieces=(1, 4, 8))
     assert n_hits > N_SAMPLE
     _frame_invariants(got)
     fused = salf.render(scene, sensor=lid, outputs=outs)
