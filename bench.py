@@ -655,7 +655,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-training", action="store_true")
-    ap.add_argument("--alone", action="store_true", help="also time each render alone after the timed region")
     ap.add_argument("--serve-ticks", type=int, default=40)
     ap.add_argument("--counter-pass", choices=("multi", "camera", "lidar", "backward"), default=None,
                     help="run only the kernels a rocprofv3 --pmc pass needs: a 512 MiB device copy (the "
@@ -730,14 +729,15 @@ def main():
                 ev[4].record(side_stream)
         main_stream.wait_stream(side_stream)
 
-    def kernel_ms(sensor, outs):
+    def kernel_ms(sensor, outs, pieces=1):
         """Average duration of one render alone (its schedule built beforehand), by HIP events on
         the stream it runs on."""
         sched = salf.render_schedule(scene, sensor=sensor)
+        salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, schedule=sched, pieces=pieces, **opts)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(args.steps):
-            salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, schedule=sched, **opts)
+            salf.render(scene, sensor=sensor, outputs=outs.keys(), out=outs, schedule=sched, pieces=pieces, **opts)
         ev1.record()
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / args.steps
@@ -791,8 +791,10 @@ def main():
     value = rays / (wall / args.steps) / 1e6
     value_multi = rays / (wall_multi / args.steps) / 1e6
     # each render alone, after the timed region
-    cam_alone_ms = kernel_ms(cam, cam_out) if args.alone else None
-    lid_alone_ms = kernel_ms(lid, lid_out) if args.alone else None
+    cam_alone_ms = kernel_ms(cam, cam_out)
+    lid_alone_ms = kernel_ms(lid, lid_out)
+    # the sweep alone with each ray's root cells shared out among P lanes (opts.pieces)
+    lid_pieces_ms = {P: kernel_ms(lid, lid_out, pieces=P) for P in (2, 4, 8)}
 
     # the same camera frame from the raw-logit scene (corner activations evaluated per hit)
     e0.record()
@@ -867,7 +869,9 @@ def main():
                   "ms_alone": None if lid_alone_ms is None else round(lid_alone_ms, 4),
                   "shaded_hits_per_ray": round(hits_lid / n_lid, 3), "algorithmic_bytes": lid_bytes,
                   "achieved_GBs": round(lid_bytes / (lid_ms * 1e-3) / 1e9, 1),
-                  "sweeps_per_s_alone": None if lid_alone_ms is None else round(1e3 / lid_alone_ms, 1)},
+                  "sweeps_per_s_alone": None if lid_alone_ms is None else round(1e3 / lid_alone_ms, 1),
+                  "ms_alone_in_pieces": {str(P): round(v, 4) for P, v in lid_pieces_ms.items()},
+                  "sweeps_per_s_alone_in_pieces": {str(P): round(1e3 / v, 1) for P, v in lid_pieces_ms.items()}},
         "event_ms_per_step": None if step_ms is None else round(step_ms, 4),
         "step": "camera render (its tile schedule built in the step) and LiDAR render on two streams",
         "scene_build_ms": round(build_ms, 3),
