@@ -14,7 +14,9 @@ render kernels.  Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
+import itertools
 import json
 import math
 import os
@@ -166,11 +168,18 @@ def frame_rays(kind, sen):
     return FISHEYE_VALID if kind == "fisheye" else sen["width"] * sen["height"]
 
 
-def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1.0):
+# server configurations (max_batch, max_inflight, max_launch_rays): launches capped at one full-HD
+# frame of rays, four in flight, so that a request completes with a launch of about its own size;
+# and whole admitted batches, two in flight
+SERVER_CONFIGS = {"served": (32, 4, 1920 * 1080), "served_whole_batches": (32, 2, 0)}
+
+
+def serving_bench(salf, torch, dev, n_ticks=500, warm_ticks=10, seed=7, pool_gib=1.0, configs=None):
     """Poisson arrivals of vehicle ticks over 4 resident scenes: plain FIFO rendering (one frame at
     a time on one stream) against the continuous-batching server, at 0.5x, 0.9x and 1.5x the plain
     capacity and in a closed loop (all ticks queued at once).  Latency = arrival to completion on
     the host monotonic clock, per frame."""
+    configs = SERVER_CONFIGS if configs is None else configs
     import numpy as np
 
     import synth
@@ -181,7 +190,7 @@ def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1
 
     def plain_run(arrivals):
         # a single worker renders queued frames in arrival order, one at a time
-        done, order, q = [], [], []
+        done, q = [], collections.deque()
         t0 = time.monotonic()
         i = 0
         frames = [(arrivals[k], f) for k, tk in enumerate(ticks) for f in tk]
@@ -193,7 +202,7 @@ def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1
             if not q:
                 time.sleep(max(0.0, frames[i][0] - now))
                 continue
-            arr, (kind, sen, si) = q.pop(0)
+            arr, (kind, sen, si) = q.popleft()
             salf.render(scenes[si], sensor=sen, outputs=OUTS[kind], **opts)
             torch.cuda.synchronize()
             done.append((kind, arr, time.monotonic() - t0, frame_rays(kind, sen)))
@@ -210,7 +219,9 @@ def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1
                 arr, (kind, sen, si) = frames[i]
                 pending[srv.submit(scenes[si], sen, outputs=OUTS[kind], **opts)] = (kind, arr, frame_rays(kind, sen))
                 i += 1
-            for tk in list(pending):
+            # requests complete about in submission order (FIFO admission, launches in order):
+            # poll the oldest ones
+            for tk in list(itertools.islice(pending, 64)):
                 r = srv.poll(tk)
                 if r is None:
                     continue
@@ -241,25 +252,32 @@ def serving_bench(salf, torch, dev, n_ticks=40, warm_ticks=3, seed=7, pool_gib=1
     rays_per_tick = sum(frame_rays(k, s) for k, s, _ in ticks[0])
     lam_p = plain_closed["mrays_s"] * 1e6 / rays_per_tick      # ticks per second the plain path sustains
     pool = int(pool_gib * (1 << 30))
-    srv = salf.Server(pool_bytes=pool, device=dev, max_batch=32, max_inflight=2)
-    progress("serving: served, closed loop")
-    served_closed = summarize(served_run(closed, srv), warm_frames)
+    servers = {name: salf.Server(pool_bytes=pool, device=dev, max_batch=mb, max_inflight=mi, max_launch_rays=mr)
+               for name, (mb, mi, mr) in configs.items()}
+    closed_loop = {"plain": plain_closed}
+    for name, srv in servers.items():
+        progress(f"serving: {name}, closed loop")
+        closed_loop[name] = summarize(served_run(closed, srv), warm_frames)
     points = []
     for load in (0.5, 0.9, 1.5):
         gaps = rng.exponential(1.0 / (load * lam_p), size=len(ticks))
         arrivals = list(np.cumsum(gaps) - gaps[0])
         progress(f"serving: Poisson arrivals at {load} x the plain capacity")
-        points.append({"load": load, "ticks_per_s": round(load * lam_p, 2),
-                       "plain": summarize(plain_run(arrivals), warm_frames),
-                       "served": summarize(served_run(arrivals, srv), warm_frames)})
-    st = srv.stats()
-    srv.close()
+        pt = {"load": load, "ticks_per_s": round(load * lam_p, 2), "plain": summarize(plain_run(arrivals), warm_frames)}
+        for name, srv in servers.items():
+            pt[name] = summarize(served_run(arrivals, srv), warm_frames)
+        points.append(pt)
+    stats = {}
+    for name, srv in servers.items():
+        st = srv.stats()
+        stats[name] = {"max_batch": configs[name][0], "max_inflight": configs[name][1],
+                       "max_launch_rays": configs[name][2], "launches": st["launches"], "pool_peak": st["pool_peak"]}
+        srv.close()
     return {"workload": "4 resident driving scenes (seeds 11-14); Poisson vehicle ticks of 6 pinhole 1920x1080 + "
                         "2 fisheye 1280x960 (190 deg) with 30 us/row rolling shutter + 2 LiDAR 64x2048",
             "rays_per_tick": rays_per_tick, "ticks": n_ticks, "warmup_ticks": warm_ticks,
             "pool_bytes": pool, "plain_capacity_ticks_per_s": round(lam_p, 2),
-            "closed_loop": {"plain": plain_closed, "served": served_closed},
-            "poisson": points, "server_launches": st["launches"], "server_pool_peak": st["pool_peak"]}
+            "closed_loop": closed_loop, "poisson": points, "servers": stats}
 
 
 # ------------------------------------------------------------------ training step (differentiation)
@@ -655,7 +673,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-training", action="store_true")
-    ap.add_argument("--serve-ticks", type=int, default=40)
+    ap.add_argument("--serve-ticks", type=int, default=500)
     ap.add_argument("--counter-pass", choices=("multi", "camera", "lidar", "backward"), default=None,
                     help="run only the kernels a rocprofv3 --pmc pass needs: a 512 MiB device copy (the "
                          "calibration of the HBM byte counters) and 3 launches of the named render")

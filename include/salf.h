@@ -532,6 +532,12 @@ typedef struct {
   size_t work_bytes;
   int32_t max_batch;     /* requests per launch, 1..256                                               */
   int32_t max_inflight;  /* launches in flight, 1..4                                                  */
+  int64_t max_launch_rays; /* rays per launch under light load: a launch takes admitted requests in
+                              order while their rays fit (at least one request), as long as the
+                              admitted, unlaunched rays fit in max_inflight such launches; past
+                              that backlog, launches take whole batches again.  A request
+                              completes when its launch does, so capped launches complete small
+                              sensors sooner.  0 = no cap; >= 0                                    */
 } salf_server_opts;
 
 typedef struct {

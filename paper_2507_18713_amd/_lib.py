@@ -76,7 +76,8 @@ class GradsIn(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("d_pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("d_work", C.c_void_p),
-                ("work_bytes", C.c_size_t), ("max_batch", C.c_int32), ("max_inflight", C.c_int32)]
+                ("work_bytes", C.c_size_t), ("max_batch", C.c_int32), ("max_inflight", C.c_int32),
+                ("max_launch_rays", C.c_int64)]
 
 
 class ServerStats(C.Structure):

@@ -587,9 +587,11 @@ _OUT_BITS = {"rgb": 1, "depth": 2, "opacity": 4, "intensity": 8}
 class Server:
     """Continuous-batching render server (salf_server_*).  Outputs of admitted requests are carved
     from a device pool of `pool_bytes` (the HBM budget); results are views into that pool, valid
-    until release()."""
+    until release().  max_launch_rays > 0 caps the rays of one launch (a request completes with
+    its launch, so smaller launches complete small sensors sooner); 0 = no cap."""
 
-    def __init__(self, pool_bytes: int, device="cuda", max_batch: int = 64, max_inflight: int = 2):
+    def __init__(self, pool_bytes: int, device="cuda", max_batch: int = 64, max_inflight: int = 2,
+                 max_launch_rays: int = 0):
         dev = torch.device(device)
         self.ctx = Context.get(dev)
         self.device = dev
@@ -599,6 +601,7 @@ class Server:
         op.pool_bytes = int(pool_bytes)
         op.max_batch = int(max_batch)
         op.max_inflight = int(max_inflight)
+        op.max_launch_rays = int(max_launch_rays)
         nbytes = C.c_size_t()
         call("salf_server_work_size", C.byref(op), C.byref(nbytes))
         self.work = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)

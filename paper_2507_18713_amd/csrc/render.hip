@@ -712,7 +712,9 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       float u[3], w[8], x[3], sdq = 0.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
-      // the forward's arithmetic, operation for operation, so T and the prefix sums match it
+      // the forward's arithmetic, operation for operation, so T matches it bit for bit (the colour and
+      // intensity prefix sums, formed per sample here, agree with its per-voxel dot products up to
+      // FP32 rounding)
       float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
       if constexpr (PAPER) {
 #pragma unroll

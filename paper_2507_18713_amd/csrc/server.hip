@@ -5,7 +5,8 @@
 //   2. admits queued requests in arrival order while their outputs fit in the HBM pool (first fit;
 //      a request that does not fit blocks the ones behind it, so admission stays FIFO),
 //   3. if a launch slot is free, launches one batched kernel over every tile of the requests
-//      admitted since the previous launch (up to max_batch requests) on that slot's stream.
+//      admitted since the previous launch (up to max_batch requests and, while the backlog is
+//      short, max_launch_rays rays) on that slot's stream.
 // With several slots, a batch starts while earlier ones are still running, so requests that arrive
 // while the GPU is busy overlap with them instead of waiting for a drain.
 #include <string.h>
@@ -159,11 +160,21 @@ struct salf_server {
 bool salf_server::launch(Slot& s) {
   s.items.clear();
   s.tickets.clear();
-  int64_t tiles = 0;
+  int64_t tiles = 0, rays = 0;
   uint32_t variants = 0;
+  // the ray cap holds while the admitted backlog fits in max_inflight capped launches; past that
+  // the GPU is the bottleneck and whole batches keep it fuller (fewer launch tails)
+  int64_t cap = opts.max_launch_rays;
+  if (cap > 0) {
+    int64_t backlog = 0;
+    for (uint64_t tk : admitted) backlog += reqs[tk].p.n;
+    if (backlog > (int64_t)opts.max_inflight * cap) cap = 0;
+  }
   while (!admitted.empty() && (int)s.items.size() < opts.max_batch) {
     Request& r = reqs[admitted.front()];
     if (!s.items.empty() && tiles + r.n_tiles > ((int64_t)1 << 30)) break;
+    if (!s.items.empty() && cap > 0 && rays + r.p.n > cap) break;
+    rays += r.p.n;
     BatchItem b;
     b.p = r.p;
     b.tile_begin = tiles;
@@ -262,6 +273,7 @@ salf_status salf_server_work_size(const salf_server_opts* opts, size_t* bytes) {
     return set_error(SALF_ERR_INVALID_ARG, "max_batch must be in [1, %d]", kMaxBatch);
   if (opts->max_inflight < 1 || opts->max_inflight > kMaxInflight)
     return set_error(SALF_ERR_INVALID_ARG, "max_inflight must be in [1, %d]", kMaxInflight);
+  if (opts->max_launch_rays < 0) return set_error(SALF_ERR_INVALID_ARG, "max_launch_rays must be >= 0");
   *bytes = (size_t)opts->max_inflight * slot_bytes(opts->max_batch);
   return SALF_OK;
 }

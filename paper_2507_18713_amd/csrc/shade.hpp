@@ -35,6 +35,12 @@ __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f
     const float4 g0 = gp[0], g1 = gp[1];
     g[0] = g0.x; g[1] = g0.y; g[2] = g0.z; g[3] = g0.w; g[4] = g1.x; g[5] = g1.y; g[6] = g1.z; g[7] = g1.w;
   }
+  // the paper field (and its SDF variant) evaluates affine forms of x; the corner fields
+  // interpolate corner values
+  constexpr bool kAffine = FIELD == SALF_FIELD_PAPER || FIELD == kFieldSdf;
+  // the colour and intensity rows are read with the density row, so that their loads are in
+  // flight during the samples (reading them after the samples, which the corner fields could,
+  // holds fewer registers but waits on the loads: slower)
   if (RGB) {
     const float4* cp = reinterpret_cast<const float4*>(rgb_row);
 #pragma unroll
@@ -49,9 +55,6 @@ __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f
     const float4 a = ip[0], b = ip[1];
     it[0] = a.x; it[1] = a.y; it[2] = a.z; it[3] = a.w; it[4] = b.x; it[5] = b.y; it[6] = b.z; it[7] = b.w;
   }
-  // the paper field (and its SDF variant) evaluates affine forms of x; the corner fields
-  // interpolate corner values
-  constexpr bool kAffine = FIELD == SALF_FIELD_PAPER || FIELD == kFieldSdf;
   float shc[3] = {0.0f, 0.0f, 0.0f};  // view-dependent colour term (paper field)
   float sdf_ha = 0.0f, sdf_ib = 0.0f;  // SDF variant: a / 2 and 1 / b
   if (FIELD == kFieldSdf) {
@@ -80,34 +83,58 @@ __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f
   float rel[3], stp[3], delta, sc;
   segment_frame(s, f, h, rS, rel, stp, delta, sc);
 
+  if (!kAffine) {
+    // Corner fields: colour and intensity are linear in the corner values, so the voxel's share
+    // of the composite, sum_k w_k sum_c b_c(u_k) v_c, is sum_c v_c W_c with W_c = sum_k w_k
+    // b_c(u_k): only the density is interpolated per sample, and each colour or intensity
+    // channel takes one dot product per voxel.
+    float W[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) W[i] = 0.0f;
+    for (int k = 0; k < S; ++k) {
+      const float fk = (float)k + 0.5f;
+      float u[3], w[8];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
+      corner_weights(u, w);
+      const float sigma = dot8(w, g);
+      const float e = __expf(-sigma * delta);
+      const float wgt = acc.T * (1.0f - e);
+      if (RGB || INT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) W[i] = fmaf(wgt, w[i], W[i]);
+      }
+      acc.D = fmaf(wgt, fmaf(fk, delta, ti), acc.D);
+      acc.T *= e;
+    }
+    if (RGB) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc.C[ch] += dot8(W, c[ch]);
+    }
+    if (INT) acc.I += dot8(W, it);
+    acc.n += 1;
+    return !(acc.T < t_min);
+  }
+
+  // the paper field and its SDF variant: colour and intensity are sigmoids of affine forms, so
+  // every sample evaluates them
   for (int k = 0; k < S; ++k) {
     const float fk = (float)k + 0.5f;
     float u[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = sample_u(rel[a], stp[a], fk, sc);
     float sigma, col[3] = {0.0f, 0.0f, 0.0f}, inten = 0.0f;
-    if (!kAffine) {
-      float w[8];
-      corner_weights(u, w);
-      sigma = dot8(w, g);
-      if (RGB) {
+    float x[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] = dot8(w, c[ch]);
-      }
-      if (INT) inten = dot8(w, it);
-    } else {
-      float x[3];
+    for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
+    const float q = fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3])));
+    sigma = FIELD == kFieldSdf ? sdf_sigma(q, sdf_ha, sdf_ib) : __expf(q);
+    if (RGB) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) x[a] = fmaf(2.0f, u[a], -1.0f);
-      const float q = fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3])));
-      sigma = FIELD == kFieldSdf ? sdf_sigma(q, sdf_ha, sdf_ib) : __expf(q);
-      if (RGB) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-          col[ch] = sigmoid_f(fmaf(c[ch][0], x[0], fmaf(c[ch][1], x[1], fmaf(c[ch][2], x[2], shc[ch]))));
-      }
-      if (INT) inten = sigmoid_f(fmaf(it[0], x[0], fmaf(it[1], x[1], fmaf(it[2], x[2], it[3]))));
+      for (int ch = 0; ch < 3; ++ch)
+        col[ch] = sigmoid_f(fmaf(c[ch][0], x[0], fmaf(c[ch][1], x[1], fmaf(c[ch][2], x[2], shc[ch]))));
     }
+    if (INT) inten = sigmoid_f(fmaf(it[0], x[0], fmaf(it[1], x[1], fmaf(it[2], x[2], it[3]))));
     const float e = __expf(-sigma * delta);
     const float wgt = acc.T * (1.0f - e);
     if (RGB) {

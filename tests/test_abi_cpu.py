@@ -50,7 +50,7 @@ int main(void) {
   printf("RenderOpts %zu %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, schedule), offsetof(salf_render_opts, work_bytes), offsetof(salf_render_opts, pieces));
   printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
-  printf("ServerOpts %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight));
+  printf("ServerOpts %zu %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight), offsetof(salf_server_opts, max_launch_rays));
   printf("ServerStats %zu %zu\n", sizeof(salf_server_stats), offsetof(salf_server_stats, inflight));
   return 0;
 }
@@ -72,7 +72,7 @@ int main(void) {
                        S.RenderOpts.pieces.offset],
         "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
-        "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset],
+        "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset, S.ServerOpts.max_launch_rays.offset],
         "ServerStats": [C.sizeof(S.ServerStats), S.ServerStats.inflight.offset],
     }
     assert got == want
@@ -164,6 +164,10 @@ def test_server_sizes_host_logic(L):
     for mb, mi in ((0, 2), (257, 2), (64, 0), (64, 5)):
         op.max_batch, op.max_inflight = mb, mi
         assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == -1
+    op.max_batch, op.max_inflight, op.max_launch_rays = 64, 2, -1
+    assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == -1
+    op.max_launch_rays = 1 << 21
+    assert lib.salf_server_work_size(C.byref(op), C.byref(n)) == 0 and n.value == two
     cam = sensor_struct(synth.config1_camera())
     assert lib.salf_server_request_bytes(C.byref(cam), 1 | 2 | 4, C.byref(n)) == 0
     px = 1920 * 1080

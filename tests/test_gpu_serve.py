@@ -231,3 +231,40 @@ def test_dropped_scene_stays_alive_until_release(salf):
     srv.close()
     del junk
 
+
+
+def test_served_requests_match_the_oracle_under_a_launch_ray_cap(salf, scenes, prepared):
+    """One pass of the sensor mix through a server whose launches hold at most 10,000 rays: every
+    request is checked against the oracle on sampled rays (last row and column included) and
+    against the same request rendered alone (bit for bit); launches respect the cap (a request
+    larger than the cap runs alone).  The mix's 38,560 rays fit in four capped launches, so the
+    backlog never lifts the cap."""
+    cap = 10000
+    assert sum(s["width"] * s["height"] for _, s in _sensors()) <= 4 * cap
+    srv = salf.Server(pool_bytes=32 << 20, device=dev(), max_batch=8, max_inflight=4, max_launch_rays=cap)
+    jobs = []
+    for j, (kind, s) in enumerate(_sensors()):
+        si = j % len(scenes)
+        print(f"submit {j}: {kind} {s['width']}x{s['height']} on scene {si}", flush=True)
+        jobs.append((srv.submit(scenes[si], s, outputs=OUTS[kind]), si, s, kind))
+    for tk, _, _, _ in jobs:
+        assert srv.wait(tk, timeout=60.0)
+    for q, (tk, si, s, kind) in enumerate(jobs):
+        res, t_sub, t_done = srv.poll(tk)
+        assert t_done >= t_sub > 0
+        alone = salf.render(scenes[si], sensor=s, outputs=OUTS[kind])
+        for k in OUTS[kind]:
+            assert torch.equal(res[k], alone[k]), (kind, k)
+        _oracle_check(res, prepared[si], s, kind, seed=100 + q)
+    # launches: requests in submission order, a new launch whenever the next request would pass the cap
+    n = [s["width"] * s["height"] for _, _, s, _ in jobs]
+    expect, acc = 0, 0
+    for r in n:
+        if acc == 0 or acc + r > cap:
+            expect, acc = expect + 1, 0
+        acc += r
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["launches"] >= expect
+    for tk, _, _, _ in jobs:
+        srv.release(tk)
+    srv.close()
