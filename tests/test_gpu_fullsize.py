@@ -3,7 +3,7 @@ a 64 x 2,048 rolling-shutter LiDAR sweep, rendered in the tiled launch the bench
 raw-logit scene and on the pre-activated scene the benchmark renders.
 
 Sampled rays are checked against the oracle one by one (bit-exact hits, outputs to tolerance):
-1,024 drawn at random per frame, plus the 128 rays the GPU found the most voxels on (the horizon
+4,096 drawn at random per frame, plus the 128 rays the GPU found the most voxels on (the horizon
 grazers, the slowest rays and the most exposed to far-field FP32; choosing which rays to check is
 the only use of a GPU value).  The oracle runs in a pool of CPU worker processes.  The whole frame
 is checked through properties that hold at any size, and the fused-raygen render is checked to
@@ -21,7 +21,7 @@ from oracle_pool import OraclePool
 from test_gpu_render import check_outputs, dev, oracle_rays, to_dev, _ray_errors
 
 pytestmark = pytest.mark.gpu
-N_SAMPLE = 1024   # random rays per frame
+N_SAMPLE = 4096   # random rays per frame
 N_HEAVY = 128     # rays with the most hits per frame
 
 
