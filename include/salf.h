@@ -351,6 +351,14 @@ salf_status salf_render_schedule(salf_context* ctx, int32_t scene_id, const salf
  *   intensity [n] I = sum w i (LiDAR intensity channel; needs a scene with intensity)
  *   t_end [n]     final transmittance T_end
  *   n_hits [n]    int32, voxels composited (the voxel that crossed t_min included)
+ *   hit_voxel, hit_t: the composited hits (salf_render and salf_render_static, one lane per ray):
+ *                 hit k of ray r (k < min(n_hits, hit_capacity)) at index k * n + r, hit_voxel
+ *                 int32 [hit_capacity, n] its voxel, hit_t float [hit_capacity, n, 2] its t_in and
+ *                 t_out; a ray's hits past hit_capacity are not stored (n_hits still counts
+ *                 them).  Both or neither; hit_t 8-byte aligned; hit_capacity >= 1 when set.
+ *                 salf_render_backward reads a ray's hits from them instead of walking the scene
+ *                 again (rays with more hits than were stored are walked).  Other entry points
+ *                 refuse them (UNSUPPORTED).
  * Colour needs a scene with colour.  Compositing runs in FP32 with FP32 transmittance. */
 typedef struct {
   float* rgb;
@@ -359,6 +367,10 @@ typedef struct {
   float* intensity;
   float* t_end;
   int32_t* n_hits;
+  int32_t* hit_voxel;
+  float* hit_t;
+  int32_t hit_capacity;
+  int32_t reserved;      /* must be 0 */
 } salf_outputs;
 
 /* Render one sensor (sensor != NULL, rays == NULL; ray generation is fused into the render

@@ -61,7 +61,8 @@ class RenderOpts(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("opacity", C.c_void_p), ("intensity", C.c_void_p),
-                ("t_end", C.c_void_p), ("n_hits", C.c_void_p)]
+                ("t_end", C.c_void_p), ("n_hits", C.c_void_p), ("hit_voxel", C.c_void_p), ("hit_t", C.c_void_p),
+                ("hit_capacity", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RenderItem(C.Structure):

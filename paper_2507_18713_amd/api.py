@@ -312,7 +312,7 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
            d: Optional[torch.Tensor] = None, samples: int = 4, t_min: float = 1e-6, background=(0.0, 0.0, 0.0),
            outputs: Iterable[str] = ("rgb", "depth", "opacity"), t_near: float = 0.0, t_far: float = math.inf,
            out: Optional[Dict[str, torch.Tensor]] = None, image_width: int = 0,
-           schedule=True, pieces: int = 1) -> Dict[str, torch.Tensor]:
+           schedule=True, pieces: int = 1, hit_capacity: int = 0) -> Dict[str, torch.Tensor]:
     """Render a sensor (ray generation fused) or explicit rays (o, d float32 [n, 3]).
     image_width > 0 declares explicit rays to be a row-major image of that width (tiled launch).
     schedule: True builds a heaviest-tiles-first schedule in the call, a buffer from
@@ -322,6 +322,9 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     pieces: lanes per ray (1; or 2, 4, 8: each ray's occupied root cells are shared out among that
     many lanes and their partial results folded front to back; the same hits, outputs equal to
     the one-lane render's up to FP32 rounding).
+    hit_capacity > 0 also stores each ray's composited hits, at most that many per ray:
+    "hit_voxel" int32 [hit_capacity, n] and "hit_t" float32 [hit_capacity, n, 2] (t_in, t_out),
+    hit k of ray r at [k, r]; render_backward then reads them instead of walking the scene again.
     Returns a dict with the requested outputs (rgb [n,3]; depth, opacity, intensity, t_end [n];
     n_hits int32 [n])."""
     dev = scene.device
@@ -344,6 +347,11 @@ def render(scene: Scene, sensor: Optional[dict] = None, o: Optional[torch.Tensor
     ob = _lib.Outputs()
     for k in OUTPUT_NAMES:
         setattr(ob, k, res[k].data_ptr() if k in res else None)
+    if hit_capacity > 0:
+        cap = int(hit_capacity)
+        res["hit_voxel"] = torch.empty((cap, n), dtype=torch.int32, device=dev)
+        res["hit_t"] = torch.empty((cap, n, 2), dtype=torch.float32, device=dev)
+        ob.hit_voxel, ob.hit_t, ob.hit_capacity = res["hit_voxel"].data_ptr(), res["hit_t"].data_ptr(), cap
     if isinstance(schedule, str):
         if schedule != "static":
             raise ValueError(f"unknown schedule {schedule!r}")
@@ -510,7 +518,9 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
                     background=(0.0, 0.0, 0.0), t_near: float = 0.0, t_far: float = math.inf,
                     d_geo=None, d_rgb=None, d_int=None, image_width: int = 0, schedule=True):
     """Accumulate dL/d(params) of a render (corner or paper field) into d_geo/d_rgb/d_int (allocated
-    zeroed if None and the scene has that parameter).  Returns (d_geo, d_rgb, d_int)."""
+    zeroed if None and the scene has that parameter).  `saved` holds the forward's outputs, with
+    its "hit_voxel" / "hit_t" if the forward stored hits (then those rays are not walked again).
+    Returns (d_geo, d_rgb, d_int)."""
     dev = scene.device
     if d_geo is None:
         d_geo = torch.zeros_like(scene.geo, memory_format=torch.contiguous_format)
@@ -527,6 +537,11 @@ def render_backward(scene: Scene, saved: Dict[str, torch.Tensor], grads: Dict[st
     for k in OUTPUT_NAMES:
         t = saved.get(k)
         setattr(sv, k, t.data_ptr() if t is not None else None)
+    if saved.get("hit_voxel") is not None:
+        hv, ht = saved["hit_voxel"], saved["hit_t"]
+        if hv.dim() != 2 or tuple(ht.shape) != (hv.shape[0], hv.shape[1], 2):
+            raise ValueError("hit_voxel [cap, n] and hit_t [cap, n, 2] expected")
+        sv.hit_voxel, sv.hit_t, sv.hit_capacity = hv.data_ptr(), ht.data_ptr(), int(hv.shape[0])
     g = _lib.GradsIn()
     for k, f in (("rgb", "d_rgb"), ("depth", "d_depth"), ("opacity", "d_opacity"), ("intensity", "d_intensity")):
         t = grads.get(k)

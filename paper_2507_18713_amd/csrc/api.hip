@@ -124,6 +124,18 @@ salf_status salf::validate_opts(const salf_render_opts* o) {
   return SALF_OK;
 }
 
+salf_status salf::check_hit_outputs(const salf_outputs* out, bool supported, const char* what) {
+  if (!out) return SALF_OK;
+  if (out->reserved != 0) return set_error(SALF_ERR_INVALID_ARG, "outputs: reserved must be 0");
+  if (!out->hit_voxel && !out->hit_t) return SALF_OK;
+  if (!supported) return set_error(SALF_ERR_UNSUPPORTED, "%s store no hit lists", what);
+  if (!out->hit_voxel || !out->hit_t) return set_error(SALF_ERR_INVALID_ARG, "hit_voxel and hit_t go together");
+  if (out->hit_capacity < 1) return set_error(SALF_ERR_INVALID_ARG, "hit_capacity must be >= 1");
+  if (((uintptr_t)out->hit_voxel & 3u) || ((uintptr_t)out->hit_t & 7u))
+    return set_error(SALF_ERR_INVALID_ARG, "hit_voxel must be 4-byte and hit_t 8-byte aligned");
+  return SALF_OK;
+}
+
 salf_status salf::one_lane_per_ray(const salf_render_opts* o, const char* what) {
   if (o && o->pieces > 1) return set_error(SALF_ERR_UNSUPPORTED, "%s walk each ray with one lane (pieces <= 1)", what);
   return SALF_OK;
@@ -568,6 +580,7 @@ salf_status salf_render(salf_context* ctx, int32_t scene_id, const salf_sensor* 
   if (out->rgb && !p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
   if (out->intensity && !p.scene.inten)
     return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
+  if ((st = check_hit_outputs(out, p.pieces <= 1, "renders in pieces"))) return st;
   p.out = *out;
   DeviceGuard g(ctx->device);
   if (opts->schedule == SALF_SCHEDULE_BUILD &&
@@ -650,6 +663,7 @@ salf_status salf_render_raster(salf_context* ctx, int32_t scene_id, const salf_s
   if (st) return st;
   if ((st = validate_opts(opts)) || (st = one_lane_per_ray(opts, "splatting renders"))) return st;
   if (!out || !n_pairs) return set_error(SALF_ERR_INVALID_ARG, "outputs and n_pairs are required");
+  if ((st = check_hit_outputs(out, false, "splatting renders"))) return st;
   if (out->rgb && !p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "colour requested from a scene without colour");
   if (out->intensity && !p.scene.inten)
     return set_error(SALF_ERR_INVALID_ARG, "intensity requested from a scene without intensity");
@@ -712,6 +726,7 @@ salf_status salf_render_multi(salf_context* ctx, int32_t n_items, const salf_ren
     if ((st = one_lane_per_ray(&o, "multi-sensor launches"))) return st;
     if ((st = prepare_render(ctx, it.scene_id, it.sensor, nullptr, &o, &b.p, &field))) return st;
     if (field != SALF_FIELD_CORNER) return set_error(SALF_ERR_UNSUPPORTED, "item %d: multi-sensor launches render corner-field scenes", i);
+    if ((st = check_hit_outputs(&it.out, false, "multi-sensor launches"))) return st;
     if (it.out.rgb && !b.p.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "item %d: colour from a scene without colour", i);
     if (it.out.intensity && !b.p.scene.inten)
       return set_error(SALF_ERR_INVALID_ARG, "item %d: intensity from a scene without intensity", i);
@@ -772,6 +787,7 @@ salf_status salf_render_composite(salf_context* ctx, int32_t static_scene_id, in
   salf_status st = one_lane_per_ray(opts, "renders with actors");
   if (st || (st = prepare_render(ctx, static_scene_id, sensor, rays, opts, &cp.base, &field))) return st;
   if (!out) return set_error(SALF_ERR_INVALID_ARG, "outputs is NULL");
+  if ((st = check_hit_outputs(out, false, "renders with actors"))) return st;
   if (n_actors < 0 || n_actors > SALF_MAX_ACTORS || (n_actors > 0 && !actors))
     return set_error(SALF_ERR_INVALID_ARG, "n_actors %d outside [0, %d] or actors NULL", n_actors, SALF_MAX_ACTORS);
   const bool act = cp.base.scene.act_geo != nullptr;
@@ -850,11 +866,19 @@ salf_status salf_render_backward(salf_context* ctx, int32_t scene_id, const salf
     return set_error(SALF_ERR_INVALID_ARG, "intensity gradient needs the saved intensity and a scene with intensity");
   if (d_drgb && !b.fwd.scene.rgb) return set_error(SALF_ERR_INVALID_ARG, "scene has no colour parameters");
   if (d_dint && !b.fwd.scene.inten) return set_error(SALF_ERR_INVALID_ARG, "scene has no intensity parameters");
+  if ((st = check_hit_outputs(saved, true, ""))) return st;
   b.fwd.out = *saved;
   b.g = *grads;
   b.dgeo = d_dgeo;
   b.drgb = d_drgb;
   b.dint = d_dint;
+  b.vbox = nullptr;
+  b.walk_only_unstored = 0;
+  if (saved->hit_voxel) {
+    Scene sc;
+    if ((st = scene_snapshot(ctx, scene_id, &sc))) return st;
+    b.vbox = sc.vbox;
+  }
   DeviceGuard g(ctx->device);
   if (opts->schedule == SALF_SCHEDULE_BUILD &&
       (st = check_hip(launch_tile_schedule(b.fwd, opts->d_work, (hipStream_t)stream), "tile schedule launch")))

@@ -208,6 +208,8 @@ struct BackwardParams {
   float* dgeo;
   float* drgb;
   float* dint;
+  const int4* vbox;    // each voxel's finest-cell box (min corner, edge): hits read from fwd.out
+  int32_t walk_only_unstored;  // walk only the rays whose hits were not all stored
 };
 // field: SALF_FIELD_CORNER or SALF_FIELD_PAPER (the scene's)
 hipError_t launch_backward(const BackwardParams& p, int field, hipStream_t stream);
@@ -243,4 +245,7 @@ salf_status validate_sensor(const salf_sensor* s);
 salf_status validate_opts(const salf_render_opts* o);
 // UNSUPPORTED when o asks for several lanes per ray (entry points whose kernels walk a ray with one lane).
 salf_status one_lane_per_ray(const salf_render_opts* o, const char* what);
+// The hit-list outputs of out: well formed, and asked only where supported (else UNSUPPORTED, `what`
+// naming the entry point); reserved must be 0.
+salf_status check_hit_outputs(const salf_outputs* out, bool supported, const char* what);
 }  // namespace salf

@@ -77,7 +77,7 @@ __device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t
 // (an opaque copy of its address keeps the compiler from loading them up front), rather than held
 // in scalar registers through it: those are short in the walk, and every extra value there is
 // spilled and reloaded inside its loops.
-template <int FIELD, bool RGB, bool INT, bool p_is_kernarg = false>
+template <int FIELD, bool RGB, bool INT, bool p_is_kernarg = false, bool HITS = false>
 __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk) {
   int64_t ray;
   float d[3];
@@ -94,7 +94,14 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const float t_min = p.t_min;
   bool cut = false;
   traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
-    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
+    const bool more = shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
+    if (HITS && acc.n <= p.out.hit_capacity) {
+      // hit k of the ray at k * n + ray: the lanes of a wave store neighbouring entries
+      const int64_t at = (int64_t)(acc.n - 1) * p.n + ray;
+      p.out.hit_voxel[at] = h.voxel;
+      reinterpret_cast<float2*>(p.out.hit_t)[at] = make_float2(h.t_in, h.t_out);
+    }
+    return more;
   }, [&] { cut = true; });
   const RenderParams* q = &p;
   if (p_is_kernarg) {
@@ -120,11 +127,11 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
 // more than the few spills the cap causes.
 #define SALF_RENDER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3)))
 
-template <int FIELD, bool RGB, bool INT>
+template <int FIELD, bool RGB, bool INT, bool HITS>
 __global__ __launch_bounds__(kThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
-  render_wave<FIELD, RGB, INT, true>(p, scheduled_tile(p, w), stk + threadIdx.x);
+  render_wave<FIELD, RGB, INT, true, HITS>(p, scheduled_tile(p, w), stk + threadIdx.x);
 }
 
 // ---- one ray in pieces
@@ -602,7 +609,10 @@ __global__ __launch_bounds__(kThreads) void raygen_kernel(salf_sensor s, float* 
 // Transmittance is recomputed front to back; the ray stops after the saved number of voxels.
 // PAPER: the field of Eq. 1-2 (raw parameters; ACT is false), with SDF its density replaced by
 // Eq. 5-6; else the corner field.
-template <bool RGB, bool INT, bool ACT, bool PAPER, bool SDF>
+// HITS: the forward stored each ray's hits (fwd.out.hit_voxel, hit_t), and the kernel reads them
+// instead of walking the scene: only rays whose hits were all stored; a second launch without
+// HITS (walk_only_unstored) walks the others.
+template <bool RGB, bool INT, bool ACT, bool PAPER, bool SDF, bool HITS>
 __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   const RenderParams& p = b.fwd;
   int64_t ray;
@@ -612,6 +622,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   if (!lane_ray(p, scheduled_tile(p, w), threadIdx.x & 63, ray, dir, f)) return;
   const int32_t n_stop = p.out.n_hits[ray];
   if (n_stop <= 0) return;
+  if (HITS ? n_stop > p.out.hit_capacity : (b.walk_only_unstored && n_stop <= p.out.hit_capacity)) return;
   const float T_end = p.out.t_end[ray];
   float gC[3] = {0.0f, 0.0f, 0.0f}, Cs[3] = {0.0f, 0.0f, 0.0f};
   if (RGB) {
@@ -642,7 +653,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   // degree-1 SH basis of the ray direction (paper field), as in the forward
   const float shb[4] = {kShC0, kShC1 * dir[0], kShC1 * dir[1], kShC1 * dir[2]};
-  traverse(s, f, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+  const auto visit = [&](const Hit& h) -> bool {
     const int32_t v = h.voxel;
     const float ti = h.t_in;
     // activated corner values (stored ones when the scene keeps them, else from the logits); for
@@ -857,7 +868,27 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       if (dst) unsafeAtomicAdd(dst, sum);
     }
     return ++count < n_stop;
-  }, note_cut);
+  };
+  if constexpr (HITS) {
+    const int32_t* hv = p.out.hit_voxel;
+    const float2* ht = reinterpret_cast<const float2*>(p.out.hit_t);
+    for (int32_t k = 0; k < n_stop; ++k) {
+      const int64_t at = (int64_t)k * p.n + ray;
+      Hit h;
+      h.voxel = hv[at];
+      const float2 t = ht[at];
+      h.t_in = t.x;
+      h.t_out = t.y;
+      const int4 bx = b.vbox[h.voxel];
+      h.lo[0] = bx.x;
+      h.lo[1] = bx.y;
+      h.lo[2] = bx.z;
+      h.size = bx.w;
+      visit(h);
+    }
+  } else {
+    traverse(s, f, stk + threadIdx.x, kThreads, visit, note_cut);
+  }
 }
 
 template <int FIELD>
@@ -871,10 +902,17 @@ hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stre
     else render_split_kernel<FIELD, false, false><<<blocks, kThreads, 0, stream>>>(p);
     return hipGetLastError();
   }
-  if (rgb && in) render_kernel<FIELD, true, true><<<blocks, kThreads, 0, stream>>>(p);
-  else if (rgb) render_kernel<FIELD, true, false><<<blocks, kThreads, 0, stream>>>(p);
-  else if (in) render_kernel<FIELD, false, true><<<blocks, kThreads, 0, stream>>>(p);
-  else render_kernel<FIELD, false, false><<<blocks, kThreads, 0, stream>>>(p);
+  if (p.out.hit_voxel != nullptr) {
+    if (rgb && in) render_kernel<FIELD, true, true, true><<<blocks, kThreads, 0, stream>>>(p);
+    else if (rgb) render_kernel<FIELD, true, false, true><<<blocks, kThreads, 0, stream>>>(p);
+    else if (in) render_kernel<FIELD, false, true, true><<<blocks, kThreads, 0, stream>>>(p);
+    else render_kernel<FIELD, false, false, true><<<blocks, kThreads, 0, stream>>>(p);
+    return hipGetLastError();
+  }
+  if (rgb && in) render_kernel<FIELD, true, true, false><<<blocks, kThreads, 0, stream>>>(p);
+  else if (rgb) render_kernel<FIELD, true, false, false><<<blocks, kThreads, 0, stream>>>(p);
+  else if (in) render_kernel<FIELD, false, true, false><<<blocks, kThreads, 0, stream>>>(p);
+  else render_kernel<FIELD, false, false, false><<<blocks, kThreads, 0, stream>>>(p);
   return hipGetLastError();
 }
 
@@ -1008,34 +1046,48 @@ hipError_t launch_render_batch(const BatchItem* d_items, int32_t n_items, int64_
   return launch_batch_mask<kBatchMasks[2]>(2, d_items, n_items, n_tiles, d_counter, d_sched, stream);
 }
 
+namespace {
+template <bool HITS>
+hipError_t launch_backward_pass(const BackwardParams& b, int field, unsigned blocks, hipStream_t stream) {
+  const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
+  const RenderParams& p = b.fwd;
+  if (field == SALF_FIELD_SDF) {
+    if (rgb && in) backward_kernel<true, true, false, true, true, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, true, true, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, true, true, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, true, true, HITS><<<blocks, kThreads, 0, stream>>>(b);
+  } else if (field == SALF_FIELD_PAPER) {
+    if (rgb && in) backward_kernel<true, true, false, true, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, true, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, true, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, true, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+  } else if (p.scene.act_geo != nullptr) {
+    if (rgb && in) backward_kernel<true, true, true, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, true, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, true, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, true, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+  } else {
+    if (rgb && in) backward_kernel<true, true, false, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (rgb) backward_kernel<true, false, false, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else if (in) backward_kernel<false, true, false, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+    else backward_kernel<false, false, false, false, false, HITS><<<blocks, kThreads, 0, stream>>>(b);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_backward(const BackwardParams& b, int field, hipStream_t stream) {
   const RenderParams& p = b.fwd;
   const int64_t threads = p.tiled ? (int64_t)p.tiles_x * p.tiles_y * 64 : p.n;
   if (threads <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
-  const bool rgb = b.g.d_rgb != nullptr, in = b.g.d_intensity != nullptr;
-  if (field == SALF_FIELD_SDF) {
-    if (rgb && in) backward_kernel<true, true, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false, true, true><<<blocks, kThreads, 0, stream>>>(b);
-  } else if (field == SALF_FIELD_PAPER) {
-    if (rgb && in) backward_kernel<true, true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false, true, false><<<blocks, kThreads, 0, stream>>>(b);
-  } else if (p.scene.act_geo != nullptr) {
-    if (rgb && in) backward_kernel<true, true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, true, false, false><<<blocks, kThreads, 0, stream>>>(b);
-  } else {
-    if (rgb && in) backward_kernel<true, true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (rgb) backward_kernel<true, false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else if (in) backward_kernel<false, true, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
-    else backward_kernel<false, false, false, false, false><<<blocks, kThreads, 0, stream>>>(b);
-  }
-  return hipGetLastError();
+  if (p.out.hit_voxel == nullptr || b.vbox == nullptr) return launch_backward_pass<false>(b, field, blocks, stream);
+  // stored hits: every ray whose hits were all stored, then a walk of the others
+  hipError_t e = launch_backward_pass<true>(b, field, blocks, stream);
+  if (e != hipSuccess) return e;
+  BackwardParams rest = b;
+  rest.walk_only_unstored = 1;
+  return launch_backward_pass<false>(rest, field, blocks, stream);
 }
 
 hipError_t launch_trace(const SceneView& s, const salf_rays& r, int32_t max_hits, int field, int32_t S, float t_min,

@@ -48,7 +48,7 @@ int main(void) {
   printf("Sensor %zu %zu %zu\n", sizeof(salf_sensor), offsetof(salf_sensor, R0), offsetof(salf_sensor, t_far));
   printf("Rays %zu %zu\n", sizeof(salf_rays), offsetof(salf_rays, t_far));
   printf("RenderOpts %zu %zu %zu %zu\n", sizeof(salf_render_opts), offsetof(salf_render_opts, schedule), offsetof(salf_render_opts, work_bytes), offsetof(salf_render_opts, pieces));
-  printf("Outputs %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits));
+  printf("Outputs %zu %zu %zu %zu\n", sizeof(salf_outputs), offsetof(salf_outputs, n_hits), offsetof(salf_outputs, hit_t), offsetof(salf_outputs, hit_capacity));
   printf("GradsIn %zu %zu\n", sizeof(salf_grads_in), offsetof(salf_grads_in, d_intensity));
   printf("ServerOpts %zu %zu %zu\n", sizeof(salf_server_opts), offsetof(salf_server_opts, max_inflight), offsetof(salf_server_opts, max_launch_rays));
   printf("ServerStats %zu %zu\n", sizeof(salf_server_stats), offsetof(salf_server_stats, inflight));
@@ -70,7 +70,7 @@ int main(void) {
         "Rays": [C.sizeof(S.Rays), S.Rays.t_far.offset],
         "RenderOpts": [C.sizeof(S.RenderOpts), S.RenderOpts.schedule.offset, S.RenderOpts.work_bytes.offset,
                        S.RenderOpts.pieces.offset],
-        "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset],
+        "Outputs": [C.sizeof(S.Outputs), S.Outputs.n_hits.offset, S.Outputs.hit_t.offset, S.Outputs.hit_capacity.offset],
         "GradsIn": [C.sizeof(S.GradsIn), S.GradsIn.d_intensity.offset],
         "ServerOpts": [C.sizeof(S.ServerOpts), S.ServerOpts.max_inflight.offset, S.ServerOpts.max_launch_rays.offset],
         "ServerStats": [C.sizeof(S.ServerStats), S.ServerStats.inflight.offset],

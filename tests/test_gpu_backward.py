@@ -342,3 +342,54 @@ def test_preactivated_scene_gives_the_same_gradient(salf):
         for name, x, y in zip(("geo", "rgb", "intensity"), gr, ga):
             assert torch.any(x != 0), name
             _close(y.cpu().numpy(), x.cpu().numpy(), rel=1e-3, absr=1e-5)
+
+
+@pytest.mark.parametrize("field,cap", [("corner", 64), ("corner", 2), ("corner-act", 64), ("paper", 64), ("sdf", 3)])
+def test_stored_hits_give_the_oracle_gradient(salf, field, cap):
+    """The forward stores each ray's composited hits (hit_capacity entries at most): they equal the
+    traced hit list with the render's early termination bit for bit, the other outputs keep their
+    bits, and the backward that reads them (walking only rays with more hits than were stored)
+    gives the oracle's gradient.  cap 2 and 3 leave many rays to the walk."""
+    if field in ("corner", "corner-act"):
+        data = synth.random_scene(91, root_dims=(5, 4, 3), max_level=2)
+    else:
+        data = _paper_scene(92) if field == "paper" else _sdf_scene(92)
+    o, d = synth.random_rays(93, 700, data.origin, data.origin + data.root_dims * data.root_size)
+    n = o.shape[0]
+    rng = np.random.default_rng(94)
+    g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+    g_d, g_o, g_i = (rng.normal(size=n).astype(np.float32) for _ in range(3))
+    bg = (0.1, 0.2, 0.3)
+    kw = dict(field=field) if field in ("paper", "sdf") else dict(preactivate=field == "corner-act")
+    scene = salf.Scene.from_data(data, device=dev(), **kw)
+    outs = ("rgb", "depth", "opacity", "intensity", "t_end", "n_hits")
+    plain = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg, outputs=outs)
+    saved = salf.render(scene, o=to_dev(o), d=to_dev(d), background=bg, outputs=outs, hit_capacity=cap)
+    for k in outs:
+        assert torch.equal(saved[k], plain[k]), k
+    nh = saved["n_hits"].cpu().numpy()
+    if cap < 8:
+        assert nh.max() > cap  # some rays are walked
+    counts, ids, ti, to = salf.trace_hits(scene, to_dev(o), to_dev(d), int(nh.max()) + 1, early_termination=True)
+    assert torch.equal(counts, saved["n_hits"])
+    hv = saved["hit_voxel"].cpu().numpy()
+    ht = saved["hit_t"].cpu().numpy()
+    ids, ti, to = ids.cpu().numpy(), ti.cpu().numpy(), to.cpu().numpy()
+    for r in range(n):
+        k = min(int(nh[r]), cap)
+        assert np.array_equal(hv[:k, r], ids[r, :k]), r
+        assert np.array_equal(ht[:k, r, 0].view(np.uint32), ti[r, :k].view(np.uint32)), r
+        assert np.array_equal(ht[:k, r, 1].view(np.uint32), to[r, :k].view(np.uint32)), r
+    grads = {"rgb": to_dev(g_rgb), "depth": to_dev(g_d), "opacity": to_dev(g_o), "intensity": to_dev(g_i)}
+    dg, dr, di = salf.render_backward(scene, saved, dict(grads), o=to_dev(o), d=to_dev(d), background=bg)
+    wg, wr, wi = salf.render_backward(scene, plain, dict(grads), o=to_dev(o), d=to_dev(d), background=bg)
+    eg, er, ei = oracle.grad_rays(oracle.prepare(data), o, d,
+                                  RenderOpts(background=bg, field="corner" if field == "corner-act" else field),
+                                  g_rgb, g_d, g_o, g_i)
+    for got, walked, ref in ((dg, wg, eg), (dr, wr, er), (di, wi, ei)):
+        got, walked = got.cpu().numpy(), walked.cpu().numpy()
+        if field == "corner-act":  # the activated copies round once more: the bar of the pre-activated test
+            _close(got, walked, rel=1e-4, absr=1e-6)
+        else:
+            _close(got, ref)
+        _close(got, walked, rel=1e-4, absr=1e-6)
