@@ -511,7 +511,9 @@ typedef struct {
  * `sensor`/`rays`, `opts` and the scene parameters must be those of the forward call, and
  * `saved` must hold its t_end and n_hits (rgb/depth/intensity as well when their gradient is
  * requested).  The kernel re-traverses each ray and recomputes transmittance front to back; no
- * per-sample state is stored.  A SALF_SCENE_PREACTIVATE scene is read through its stored
+ * per-sample state is stored.  When `saved` also holds the forward's stored hits (hit_voxel,
+ * hit_t, hit_capacity as the forward wrote them), a ray whose hits were all stored is not
+ * traversed again: its hits are read in order (a second launch walks the other rays).  A SALF_SCENE_PREACTIVATE scene is read through its stored
  * activated values in both passes (salf_scene_refresh after changing the logits), softplus'
  * being taken as 1 - exp(-softplus); the gradient is w.r.t. the logits either way.  Lanes of a
  * wave that hit the same voxel add their contributions first; the rest is accumulated with FP32
