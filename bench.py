@@ -281,7 +281,9 @@ def serving_bench(salf, torch, dev, n_ticks=500, warm_ticks=10, seed=7, pool_gib
 
 
 # ------------------------------------------------------------------ training step (differentiation)
-HIT_CAPACITY = 256  # hits stored per ray by the training forward (a camera ray of the driving scene shades <= 172)
+# hits stored per ray by the training forward for the LiDAR batch, whose backward then does not walk
+# its long rays again (the camera batch's backward walks: reading stored hits was slower there)
+HIT_CAPACITY = 256
 
 
 def training_bench(salf, torch, dev, data, steps=10, seed=4):
@@ -341,8 +343,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     def step(ev=None, cap=HIT_CAPACITY):
         d_geo.zero_()
         d_rgb.zero_()
-        # the forward stores each ray's hits, which the backward reads instead of walking again
-        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, hit_capacity=cap, **opts)
+        # the LiDAR forward stores each ray's hits, which its backward reads instead of walking again
+        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, **opts)
         fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), hit_capacity=cap, **opts)
         g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
         g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
@@ -370,7 +372,7 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     loss = float(torch.mean((fc["rgb"] - tgt_c) ** 2) + torch.mean(torch.abs(fl["depth"] - tgt_d)))
     ms = float(np.median(times))
     grad_abs_sum = float(d_geo.abs().sum() + d_rgb.abs().sum())
-    # the same step with the backward walking the scene again (no stored hits), for comparison
+    # the same step with both backwards walking the scene again (no stored hits), for comparison
     walk_times, walk_fwd = [], []
     for _ in range(steps // 2 + 1):
         e0, em, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -387,8 +389,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     sdf = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, field="sdf")
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
                         "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
-                        "SGD update + activation refresh in the step; the forward stores each ray's hits "
-                        f"(up to {HIT_CAPACITY}) and the backward reads them",
+                        "SGD update + activation refresh in the step; the LiDAR forward stores each ray's hits "
+                        f"(up to {HIT_CAPACITY}) and its backward reads them",
             "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),
@@ -590,7 +592,7 @@ def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, ste
     for i in range(steps + 2):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        fc = salf.render(scene, o=oc, d=dc, outputs=outs, hit_capacity=HIT_CAPACITY, **opts)
+        fc = salf.render(scene, o=oc, d=dc, outputs=outs, **opts)
         fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), hit_capacity=HIT_CAPACITY,
                          **opts)
         e1.record()
