@@ -152,3 +152,27 @@ def test_raster_work_area_and_unsupported_sensors(salf):
     r = salf.render_raster(es, cam, background=(0.25, 0.5, 0.75), outputs=("rgb", "opacity", "n_hits"))
     assert torch.all(r["rgb"] == torch.tensor([0.25, 0.5, 0.75], device=dev()))
     assert torch.all(r["opacity"] == 0) and torch.all(r["n_hits"] == 0)
+
+
+def test_splatted_frame_trains_through_the_ray_cast_backward(salf):
+    """The splatted frame is the ray cast's bits, so the ray-casting backward of the same camera is
+    its gradient: fed the splatted outputs, it gives the gradient it gives fed the ray cast's (up to
+    the order of its atomic additions); the ray-casting backward itself is checked against the
+    oracle's analytic gradient and central differences in the backward tests."""
+    from test_gpu_backward import _close
+    data = synth.random_scene(311, root_dims=(5, 4, 3), max_level=2, fill=0.7)
+    scene = salf.Scene.from_data(data, device=dev())
+    cam = _cameras(data, 48, 36)[0]
+    bg = (0.1, 0.2, 0.3)
+    splat = salf.render_raster(scene, cam, background=bg, outputs=OUTS)
+    cast = salf.render(scene, sensor=cam, background=bg, outputs=OUTS)
+    _equal(splat, cast, OUTS)
+    n = cam["width"] * cam["height"]
+    rng = np.random.default_rng(312)
+    grads = {k: torch.from_numpy(rng.normal(size=(n, 3) if k == "rgb" else n).astype(F32)).to(dev())
+             for k in ("rgb", "depth", "opacity", "intensity")}
+    gs = salf.render_backward(scene, splat, dict(grads), sensor=cam, background=bg)
+    gc = salf.render_backward(scene, cast, dict(grads), sensor=cam, background=bg)
+    for a, b in zip(gs, gc):
+        assert torch.any(b != 0)
+        _close(a.cpu().numpy(), b.cpu().numpy(), rel=1e-5, absr=1e-7)
