@@ -47,9 +47,9 @@ def _c_render(salf, entry, scene, sensor):
     n = sensor["width"] * sensor["height"]
     res = {k: torch.full((n, 3) if k == "rgb" else (n,), -1 if k == "n_hits" else math.nan,
                          dtype=torch.int32 if k == "n_hits" else torch.float32, device=dev) for k in OUTS}
-    ob = _lib.Outputs()
-    for k in _lib.Outputs._fields_:
-        setattr(ob, k[0], res[k[0]].data_ptr() if k[0] in res else None)
+    ob = _lib.Outputs()  # zero-filled: no intensity, no stored hits
+    for k in OUTS:
+        setattr(ob, k, res[k].data_ptr())
     sen = sensor_struct(sensor)
     opts = _lib.RenderOpts()
     opts.samples_per_voxel, opts.t_min = 4, 1e-6
