@@ -857,15 +857,28 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     }
     const int size = __popcll(mine);
     const int rank = __popcll(mine & ((1ull << lane) - 1ull));
-    for (int j = rank; j < kRows; j += size) {
+    const auto row_dst = [&](int j) -> float* {
       // the paper field's unused record slots get no atomics
-      if (PAPER && (j < 8 ? j >= (SDF ? 6 : 4) : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) continue;
-      float sum = 0.0f;
-      for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
-      float* dst = j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
-                         : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)v * 24 + (j - 8) : nullptr)
-                                          : (b.dint ? b.dint + (int64_t)v * 8 + (j - kIntRow) : nullptr));
-      if (dst) unsafeAtomicAdd(dst, sum);
+      if (PAPER && (j < 8 ? j >= (SDF ? 6 : 4) : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) return nullptr;
+      return j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
+                   : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)v * 24 + (j - 8) : nullptr)
+                                    : (b.dint ? b.dint + (int64_t)v * 8 + (j - kIntRow) : nullptr));
+    };
+    if (size == 1) {
+      // no other lane of this pass hit the voxel: its own rows go out as they are
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        float* dst = row_dst(j);
+        if (dst) unsafeAtomicAdd(dst, red[j * kRedStride + lane]);
+      }
+    } else {
+      for (int j = rank; j < kRows; j += size) {
+        float* dst = row_dst(j);
+        if (!dst) continue;
+        float sum = 0.0f;
+        for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
+        unsafeAtomicAdd(dst, sum);
+      }
     }
     return ++count < n_stop;
   };
