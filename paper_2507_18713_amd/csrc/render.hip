@@ -856,27 +856,37 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       pending &= ~m;
     }
     const int size = __popcll(mine);
-    const int rank = __popcll(mine & ((1ull << lane) - 1ull));
-    const auto row_dst = [&](int j) -> float* {
-      // the paper field's unused record slots get no atomics
+    // row j of voxel w (nullptr: not wanted, or a slot the paper field's record does not use)
+    const auto row_dst = [&](int32_t w, int j) -> float* {
       if (PAPER && (j < 8 ? j >= (SDF ? 6 : 4) : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) return nullptr;
-      return j < 8 ? (b.dgeo ? b.dgeo + (int64_t)v * 8 + j : nullptr)
-                   : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)v * 24 + (j - 8) : nullptr)
-                                    : (b.dint ? b.dint + (int64_t)v * 8 + (j - kIntRow) : nullptr));
+      return j < 8 ? (b.dgeo ? b.dgeo + (int64_t)w * 8 + j : nullptr)
+                   : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)w * 24 + (j - 8) : nullptr)
+                                    : (b.dint ? b.dint + (int64_t)w * 8 + (j - kIntRow) : nullptr));
     };
     if (size == 1) {
       // no other lane of this pass hit the voxel: its own rows go out as they are
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
-        float* dst = row_dst(j);
+        float* dst = row_dst(v, j);
         if (dst) unsafeAtomicAdd(dst, red[j * kRedStride + lane]);
       }
-    } else {
-      for (int j = rank; j < kRows; j += size) {
-        float* dst = row_dst(j);
+    }
+    // the groups of two or more lanes, one at a time, every lane of the pass helping: a group's
+    // member mask is uniform, so its members are walked with scalar instructions while each lane
+    // adds one row over them
+    const uint64_t act = __ballot(1);
+    const int nact = __popcll(act), me = __popcll(act & ((1ull << lane) - 1ull));
+    for (uint64_t heads = __ballot(size > 1 && (mine & ((1ull << lane) - 1ull)) == 0); heads; heads &= heads - 1ull) {
+      const int ld = __ffsll((long long)heads) - 1;
+      const uint32_t m_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, ld);
+      const uint32_t m_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), ld);
+      const uint64_t members = (uint64_t)m_lo | ((uint64_t)m_hi << 32);
+      const int32_t vg = __builtin_amdgcn_readlane(v, ld);
+      for (int j = me; j < kRows; j += nact) {
+        float* dst = row_dst(vg, j);
         if (!dst) continue;
         float sum = 0.0f;
-        for (uint64_t m = mine; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
+        for (uint64_t m = members; m; m &= m - 1ull) sum += red[j * kRedStride + (__ffsll((long long)m) - 1)];
         unsafeAtomicAdd(dst, sum);
       }
     }
