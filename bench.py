@@ -281,8 +281,8 @@ def serving_bench(salf, torch, dev, n_ticks=500, warm_ticks=10, seed=7, pool_gib
 
 
 # ------------------------------------------------------------------ training step (differentiation)
-# hits stored per ray by the training forward for the LiDAR batch, whose backward then does not walk
-# its long rays again (the camera batch's backward walks: reading stored hits was slower there)
+# hits stored per ray by the training forward (camera and LiDAR batches), whose backward then reads
+# them instead of walking the scene again; a ray with more hits is walked
 HIT_CAPACITY = 256
 
 
@@ -343,8 +343,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     def step(ev=None, cap=HIT_CAPACITY):
         d_geo.zero_()
         d_rgb.zero_()
-        # the LiDAR forward stores each ray's hits, which its backward reads instead of walking again
-        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, **opts)
+        # the forwards store each ray's hits, which the backwards read instead of walking again
+        fc = salf.render(scene, o=oc, d=dc, outputs=saved_outs, hit_capacity=cap, **opts)
         fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), hit_capacity=cap, **opts)
         g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
         g_l = (1.0 / n_lid) * torch.sign(fl["depth"] - tgt_d)
@@ -389,8 +389,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     sdf = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, field="sdf")
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
                         "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
-                        "SGD update + activation refresh in the step; the LiDAR forward stores each ray's hits "
-                        f"(up to {HIT_CAPACITY}) and its backward reads them",
+                        "SGD update + activation refresh in the step; the forwards store each ray's hits "
+                        f"(up to {HIT_CAPACITY}) and the backwards read them",
             "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
             "forward_ms_median": round(float(np.median(fwd)), 3),
             "backward_ms_median": round(ms - float(np.median(fwd)), 3),
@@ -592,7 +592,7 @@ def paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, ste
     for i in range(steps + 2):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
-        fc = salf.render(scene, o=oc, d=dc, outputs=outs, **opts)
+        fc = salf.render(scene, o=oc, d=dc, outputs=outs, hit_capacity=HIT_CAPACITY, **opts)
         fl = salf.render(scene, o=ol, d=dl, outputs=("depth", "opacity", "t_end", "n_hits"), hit_capacity=HIT_CAPACITY,
                          **opts)
         e1.record()

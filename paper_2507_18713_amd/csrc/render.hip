@@ -649,6 +649,10 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
   constexpr int kRedStride = 65;
   __shared__ float red_all[(kThreads / 64) * kRows * kRedStride];
   float* red = red_all + (threadIdx.x >> 6) * (kRows * kRedStride);
+  // per-wave list of the lanes whose voxel no other lane of the pass hit, and their voxels
+  __shared__ int32_t one_all[2 * kThreads];
+  int32_t* one_lane = one_all + (threadIdx.x >> 6) * 128;
+  int32_t* one_vox = one_lane + 64;
   const int lane = threadIdx.x & 63;
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
   // degree-1 SH basis of the ray direction (paper field), as in the forward
@@ -844,9 +848,9 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // Lanes that hit the same voxel at this point form a group; its members split the rows among
-    // themselves, add the group's entries of each row in lane order and issue one atomic per value,
-    // instead of one atomic per value and lane on the same addresses.
+    // Lanes that hit the same voxel at this point form a group; the group's rows are added over
+    // its members and sent out with one atomic per value, instead of one atomic per value and
+    // lane on the same addresses.
     uint64_t pending = __ballot(1), mine = 0;
     while (pending) {
       const int leader = __ffsll((long long)pending) - 1;
@@ -856,6 +860,18 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
       pending &= ~m;
     }
     const int size = __popcll(mine);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t ones = __ballot(size == 1);
+    if constexpr (HITS) {
+      if (size == 1) {
+        const int r = __popcll(ones & below);
+        one_lane[r] = lane;
+        one_vox[r] = v;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     // row j of voxel w (nullptr: not wanted, or a slot the paper field's record does not use)
     const auto row_dst = [&](int32_t w, int j) -> float* {
       if (PAPER && (j < 8 ? j >= (SDF ? 6 : 4) : (RGB && j < 32 ? ((j - 8) & 7) == 7 : j - kIntRow >= 4))) return nullptr;
@@ -863,8 +879,21 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
                    : (RGB && j < 32 ? (b.drgb ? b.drgb + (int64_t)w * 24 + (j - 8) : nullptr)
                                     : (b.dint ? b.dint + (int64_t)w * 8 + (j - kIntRow) : nullptr));
     };
-    if (size == 1) {
-      // no other lane of this pass hit the voxel: its own rows go out as they are
+    const uint64_t act = __ballot(1);
+    const int nact = __popcll(act), me = __popcll(act & below);
+    // voxels that no other lane of the pass hit: their rows go out as they are.  Reading stored
+    // hits, the lanes run in lock step and most of the wave is in every pass: the lanes take
+    // consecutive (voxel, row) pairs, so that one atomic instruction writes whole rows of one or
+    // two voxels (a few memory requests) instead of one value of each lane's own voxel (one
+    // request per lane).  Walking, fewer lanes share a pass and each sends its own rows.
+    if constexpr (HITS) {
+      const int n_one = __popcll(ones) * kRows;
+      for (int t = me; t < n_one; t += nact) {
+        const int k = t / kRows, j = t - k * kRows;
+        float* dst = row_dst(one_vox[k], j);
+        if (dst) unsafeAtomicAdd(dst, red[j * kRedStride + one_lane[k]]);
+      }
+    } else if (size == 1) {
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         float* dst = row_dst(v, j);
@@ -874,9 +903,7 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(BackwardParams b) {
     // the groups of two or more lanes, one at a time, every lane of the pass helping: a group's
     // member mask is uniform, so its members are walked with scalar instructions while each lane
     // adds one row over them
-    const uint64_t act = __ballot(1);
-    const int nact = __popcll(act), me = __popcll(act & ((1ull << lane) - 1ull));
-    for (uint64_t heads = __ballot(size > 1 && (mine & ((1ull << lane) - 1ull)) == 0); heads; heads &= heads - 1ull) {
+    for (uint64_t heads = __ballot(size > 1 && (mine & below) == 0); heads; heads &= heads - 1ull) {
       const int ld = __ffsll((long long)heads) - 1;
       const uint32_t m_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, ld);
       const uint32_t m_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), ld);
