@@ -94,14 +94,16 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const float t_min = p.t_min;
   bool cut = false;
   traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
-    const bool more = shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
-    if (HITS && acc.n <= p.out.hit_capacity) {
+    // every visited voxel is shaded, so the hit's index is the count before shading; stored before
+    // the shading, whose arithmetic then covers the stores' latency (the next step's loads would
+    // otherwise wait for them)
+    if (HITS && acc.n < p.out.hit_capacity) {
       // hit k of the ray at k * n + ray: the lanes of a wave store neighbouring entries
-      const int64_t at = (int64_t)(acc.n - 1) * p.n + ray;
+      const int64_t at = (int64_t)acc.n * p.n + ray;
       p.out.hit_voxel[at] = h.voxel;
       reinterpret_cast<float2*>(p.out.hit_t)[at] = make_float2(h.t_in, h.t_out);
     }
-    return more;
+    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
   }, [&] { cut = true; });
   const RenderParams* q = &p;
   if (p_is_kernarg) {
