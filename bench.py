@@ -646,8 +646,9 @@ def counter_pass(salf, torch, dev, data, what="multi"):
     """Kernels for a rocprofv3 --pmc run: a plain device copy of COPY_BYTES (reads and writes
     exactly that many bytes: the counters' calibration), then three launches of `what` on the
     pre-activated driving scene: "camera" the frame's render (the roofline's kernel), "lidar" the
-    sweep's, "multi" both in one launch, "backward" the camera frame's
-    backward (corner field, colour gradient) ."""
+    sweep's, "multi" both in one launch, "backward" the camera frame's backward (corner field,
+    colour gradient) reading the hits its forward stored, as the training step does,
+    "backward_walk" the same backward walking the scene again."""
     import synth
     src = torch.ones(COPY_BYTES // 4, device=dev)
     dst = torch.empty_like(src)
@@ -661,8 +662,9 @@ def counter_pass(salf, torch, dev, data, what="multi"):
     lid_out = {k: torch.empty(n_lid, device=dev) for k in ("depth", "intensity", "opacity")}
     opts = dict(samples=4, t_min=1e-6)
     saved = None
-    if what == "backward":
-        saved = salf.render(scene, sensor=cam, outputs=("rgb", "depth", "opacity", "t_end", "n_hits"), **opts)
+    if what.startswith("backward"):
+        saved = salf.render(scene, sensor=cam, outputs=("rgb", "depth", "opacity", "t_end", "n_hits"),
+                            hit_capacity=HIT_CAPACITY if what == "backward" else 0, **opts)
         grads = {"rgb": torch.full_like(saved["rgb"], 1e-3)}
         d_geo, d_rgb = torch.zeros_like(scene.geo), torch.zeros_like(scene.rgb)
     for _ in range(3):
@@ -675,7 +677,7 @@ def counter_pass(salf, torch, dev, data, what="multi"):
         else:
             salf.render_backward(scene, saved, dict(grads), sensor=cam, d_geo=d_geo, d_rgb=d_rgb, **opts)
     torch.cuda.synchronize()
-    rays = {"multi": n_cam + n_lid, "camera": n_cam, "lidar": n_lid, "backward": n_cam}[what]
+    rays = {"multi": n_cam + n_lid, "camera": n_cam, "lidar": n_lid, "backward": n_cam, "backward_walk": n_cam}[what]
     print(json.dumps({"counter_pass": what, "copy_bytes": COPY_BYTES, "rays": rays,
                       "kernel_source_hash": kernel_source_hash()}), flush=True)
 
@@ -695,7 +697,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--serve-ticks", type=int, default=500)
-    ap.add_argument("--counter-pass", choices=("multi", "camera", "lidar", "backward"), default=None,
+    ap.add_argument("--counter-pass", choices=("multi", "camera", "lidar", "backward", "backward_walk"), default=None,
                     help="run only the kernels a rocprofv3 --pmc pass needs: a 512 MiB device copy (the "
                          "calibration of the HBM byte counters) and 3 launches of the named render")
     args = ap.parse_args()
