@@ -393,3 +393,35 @@ def test_stored_hits_give_the_oracle_gradient(salf, field, cap):
         else:
             _close(got, ref)
         _close(got, walked, rel=1e-4, absr=1e-6)
+
+
+def test_backwards_on_two_streams_add_into_one_gradient(salf):
+    """Two batches' backwards launched on two streams at once (one reading stored hits, one
+    walking) add into the same gradient buffers with their atomics, as the training step's camera
+    and LiDAR batches do: the sum is the oracle's gradient of both batches together."""
+    data = synth.random_scene(95, root_dims=(5, 4, 3), max_level=2)
+    o, d = synth.random_rays(96, 1400, data.origin, data.origin + data.root_dims * data.root_size)
+    n, na = o.shape[0], 900
+    rng = np.random.default_rng(97)
+    g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+    g_d = rng.normal(size=n).astype(np.float32)
+    scene = salf.Scene.from_data(data, device=dev())
+    outs = ("rgb", "depth", "opacity", "t_end", "n_hits")
+    oa, da, ob, db = to_dev(o[:na]), to_dev(d[:na]), to_dev(o[na:]), to_dev(d[na:])
+    sa = salf.render(scene, o=oa, d=da, outputs=outs, hit_capacity=64)
+    sb = salf.render(scene, o=ob, d=db, outputs=outs)
+    ga = {"rgb": to_dev(g_rgb[:na]), "depth": to_dev(g_d[:na])}
+    gb = {"rgb": to_dev(g_rgb[na:]), "depth": to_dev(g_d[na:])}
+    d_geo, d_rgb = torch.zeros_like(scene.geo), torch.zeros_like(scene.rgb)
+    main = torch.cuda.current_stream(dev())
+    side = torch.cuda.Stream(device=dev())  # default priority
+    side.wait_stream(main)
+    with torch.cuda.stream(side):
+        salf.render_backward(scene, sb, dict(gb), o=ob, d=db, d_geo=d_geo, d_rgb=d_rgb)
+    salf.render_backward(scene, sa, dict(ga), o=oa, d=da, d_geo=d_geo, d_rgb=d_rgb)
+    main.wait_stream(side)
+    torch.cuda.synchronize()
+    zero = np.zeros(n, np.float32)
+    eg, er, _ = oracle.grad_rays(oracle.prepare(data), o, d, RenderOpts(), g_rgb, g_d, zero, zero)
+    _close(d_geo.cpu().numpy(), eg)
+    _close(d_rgb.cpu().numpy(), er)
