@@ -78,7 +78,8 @@ __device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t
 // in scalar registers through it: those are short in the walk, and every extra value there is
 // spilled and reloaded inside its loops.
 template <int FIELD, bool RGB, bool INT, bool p_is_kernarg = false, bool HITS = false>
-__device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk) {
+__device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk,
+                                            int stk_stride = kThreads) {
   int64_t ray;
   float d[3];
   RayFrame f;
@@ -93,7 +94,7 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const double rS = 1.0 / S;
   const float t_min = p.t_min;
   bool cut = false;
-  traverse(p.scene, f, stk, kThreads, [&](const Hit& h) -> bool {
+  traverse(p.scene, f, stk, stk_stride, [&](const Hit& h) -> bool {
     // every visited voxel is shaded, so the hit's index is the count before shading; stored before
     // the shading, whose arithmetic then covers the stores' latency (the next step's loads would
     // otherwise wait for them)
@@ -129,11 +130,17 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
 // more than the few spills the cap causes.
 #define SALF_RENDER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3)))
 
+// One wave per workgroup.  Waves of one launch differ in length by an order of magnitude (tiles on
+// the horizon against sky or near ground); a workgroup of four waves holds its compute unit's
+// slots until all four are placed, and the slot a finished wave frees stays idle until enough
+// are free for a whole new workgroup, while a one-wave workgroup takes any free slot at once.
+constexpr int kRenderThreads = 64;
+
 template <int FIELD, bool RGB, bool INT, bool HITS>
-__global__ __launch_bounds__(kThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
-  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
-  const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
-  render_wave<FIELD, RGB, INT, true, HITS>(p, scheduled_tile(p, w), stk + threadIdx.x);
+__global__ __launch_bounds__(kRenderThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kRenderThreads];
+  const int64_t w = blockIdx.x;
+  render_wave<FIELD, RGB, INT, true, HITS>(p, scheduled_tile(p, w), stk + threadIdx.x, kRenderThreads);
 }
 
 // ---- one ray in pieces
@@ -955,16 +962,16 @@ hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stre
     return hipGetLastError();
   }
   if (p.out.hit_voxel != nullptr) {
-    if (rgb && in) render_kernel<FIELD, true, true, true><<<blocks, kThreads, 0, stream>>>(p);
-    else if (rgb) render_kernel<FIELD, true, false, true><<<blocks, kThreads, 0, stream>>>(p);
-    else if (in) render_kernel<FIELD, false, true, true><<<blocks, kThreads, 0, stream>>>(p);
-    else render_kernel<FIELD, false, false, true><<<blocks, kThreads, 0, stream>>>(p);
+    if (rgb && in) render_kernel<FIELD, true, true, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else if (rgb) render_kernel<FIELD, true, false, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else if (in) render_kernel<FIELD, false, true, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else render_kernel<FIELD, false, false, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
     return hipGetLastError();
   }
-  if (rgb && in) render_kernel<FIELD, true, true, false><<<blocks, kThreads, 0, stream>>>(p);
-  else if (rgb) render_kernel<FIELD, true, false, false><<<blocks, kThreads, 0, stream>>>(p);
-  else if (in) render_kernel<FIELD, false, true, false><<<blocks, kThreads, 0, stream>>>(p);
-  else render_kernel<FIELD, false, false, false><<<blocks, kThreads, 0, stream>>>(p);
+  if (rgb && in) render_kernel<FIELD, true, true, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+  else if (rgb) render_kernel<FIELD, true, false, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+  else if (in) render_kernel<FIELD, false, true, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+  else render_kernel<FIELD, false, false, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
   return hipGetLastError();
 }
 
