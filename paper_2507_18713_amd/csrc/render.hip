@@ -152,13 +152,13 @@ __global__ __launch_bounds__(kRenderThreads) SALF_RENDER_OCCUPANCY void render_k
 // the voxel a one-lane walk stops after (up to the rounding of T).  For launches with too few rays
 // to fill the GPU: a long ray's cells are walked side by side instead of one after another.
 template <int FIELD, bool RGB, bool INT>
-__global__ __launch_bounds__(kThreads) void render_split_kernel(RenderParams p) {
-  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+__global__ __launch_bounds__(kRenderThreads) void render_split_kernel(RenderParams p) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kRenderThreads];
   const int P = p.pieces;
   const int lane = threadIdx.x & 63;
   const int g = lane & (P - 1);
   const int base = lane - g;
-  const int64_t w = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  const int64_t w = (blockIdx.x * (int64_t)kRenderThreads + threadIdx.x) >> 6;
   int64_t ray;
   float d[3];
   RayFrame f;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void render_split_kernel(RenderParams p) 
     if (has) {
       Hit h;
       // a partial may stop once its own T < t_min: the ray's T (no larger) is below it too
-      walk_cell(s, f, job, my_stk, kThreads, budget, h, [&](const Hit& x) -> bool {
+      walk_cell(s, f, job, my_stk, kRenderThreads, budget, h, [&](const Hit& x) -> bool {
         return shade_voxel<FIELD, RGB, INT>(s, f, sh, x, S, rS, t_min, part);
       });
       if (budget <= 0) {
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void render_split_kernel(RenderParams p) 
         if (g == j) {
           Hit h;
           int again = s.step_budget;
-          walk_cell(s, f, job, my_stk, kThreads, again, h, [&](const Hit& x) -> bool {
+          walk_cell(s, f, job, my_stk, kRenderThreads, again, h, [&](const Hit& x) -> bool {
             return shade_voxel<FIELD, RGB, INT>(s, f, sh, x, S, rS, t_min, acc);
           });
         }
@@ -279,17 +279,17 @@ __device__ __forceinline__ void actor_ray(const ActorPose& a, const float o[3], 
 // the actor inside it (in its frame), and so on, compositing every hit in that order; shading and
 // compositing are those of render_wave.
 template <int FIELD, bool RGB, bool INT>
-__global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp) {
-  __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+__global__ __launch_bounds__(kRenderThreads) void composite_kernel(CompositeParams cp) {
+  __shared__ int32_t stk[SALF_MAX_LEVEL * kRenderThreads];
   const RenderParams& p = cp.base;
-  const int64_t wave = (blockIdx.x * (int64_t)kThreads + threadIdx.x) >> 6;
+  const int64_t wave = (blockIdx.x * (int64_t)kRenderThreads + threadIdx.x) >> 6;
   int64_t ray;
   float dir[3];
   RayFrame f;
   if (!lane_ray(p, scheduled_tile(p, wave), threadIdx.x & 63, ray, dir, f)) return;
   const float sh[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // (corner field: no view-dependent term)
   // each lane's actor-box intervals, kept in LDS rather than registers (read once per piece)
-  __shared__ float a_in[kMaxActors][kThreads], a_out[kMaxActors][kThreads];
+  __shared__ float a_in[kMaxActors][kRenderThreads], a_out[kMaxActors][kRenderThreads];
   const int lt = threadIdx.x;
 #pragma unroll
   for (int a = 0; a < kMaxActors; ++a) {
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
   // actor inside its box.  Each round every live lane picks its next piece; the wave then runs
   // over the scene slots (static, actor 0, 1, ...) in step, the lanes whose piece is in slot k
   // walking it, so that the walked scene is uniform and one walk serves every slot.
-  __shared__ float ray_o[3][kThreads], ray_d[3][kThreads], ray_tf[kThreads];
+  __shared__ float ray_o[3][kRenderThreads], ray_d[3][kRenderThreads], ray_tf[kRenderThreads];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     ray_o[a][lt] = f.o[a];
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void composite_kernel(CompositeParams cp)
         actor_ray(cp.slot[k], o, d, oa, da);
       }
       const RayFrame fr = make_frame(sv, oa, da, t0, t1);
-      traverse(sv, fr, stk + threadIdx.x, kThreads, [&](const Hit& h) -> bool {
+      traverse(sv, fr, stk + threadIdx.x, kRenderThreads, [&](const Hit& h) -> bool {
         alive = shade_voxel<FIELD, RGB, INT>(sv, fr, sh, h, S, rS, t_min, acc);
         return alive;
       }, note_cut);
@@ -955,10 +955,10 @@ hipError_t launch_field(const RenderParams& p, unsigned blocks, hipStream_t stre
   const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
   if (p.pieces > 1) {
     blocks *= (unsigned)p.pieces;
-    if (rgb && in) render_split_kernel<FIELD, true, true><<<blocks, kThreads, 0, stream>>>(p);
-    else if (rgb) render_split_kernel<FIELD, true, false><<<blocks, kThreads, 0, stream>>>(p);
-    else if (in) render_split_kernel<FIELD, false, true><<<blocks, kThreads, 0, stream>>>(p);
-    else render_split_kernel<FIELD, false, false><<<blocks, kThreads, 0, stream>>>(p);
+    if (rgb && in) render_split_kernel<FIELD, true, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else if (rgb) render_split_kernel<FIELD, true, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else if (in) render_split_kernel<FIELD, false, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
+    else render_split_kernel<FIELD, false, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(p);
     return hipGetLastError();
   }
   if (p.out.hit_voxel != nullptr) {
@@ -1042,15 +1042,15 @@ hipError_t launch_composite(const CompositeParams& cp, bool activated, hipStream
   const bool rgb = p.out.rgb != nullptr, in = p.out.intensity != nullptr;
   constexpr int A = kFieldCornerActivated, C = SALF_FIELD_CORNER;
   if (activated) {
-    if (rgb && in) composite_kernel<A, true, true><<<blocks, kThreads, 0, stream>>>(cp);
-    else if (rgb) composite_kernel<A, true, false><<<blocks, kThreads, 0, stream>>>(cp);
-    else if (in) composite_kernel<A, false, true><<<blocks, kThreads, 0, stream>>>(cp);
-    else composite_kernel<A, false, false><<<blocks, kThreads, 0, stream>>>(cp);
+    if (rgb && in) composite_kernel<A, true, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else if (rgb) composite_kernel<A, true, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else if (in) composite_kernel<A, false, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else composite_kernel<A, false, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
   } else {
-    if (rgb && in) composite_kernel<C, true, true><<<blocks, kThreads, 0, stream>>>(cp);
-    else if (rgb) composite_kernel<C, true, false><<<blocks, kThreads, 0, stream>>>(cp);
-    else if (in) composite_kernel<C, false, true><<<blocks, kThreads, 0, stream>>>(cp);
-    else composite_kernel<C, false, false><<<blocks, kThreads, 0, stream>>>(cp);
+    if (rgb && in) composite_kernel<C, true, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else if (rgb) composite_kernel<C, true, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else if (in) composite_kernel<C, false, true><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
+    else composite_kernel<C, false, false><<<blocks * (kThreads / kRenderThreads), kRenderThreads, 0, stream>>>(cp);
   }
   return hipGetLastError();
 }
