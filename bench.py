@@ -355,8 +355,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
             ev.record()
         salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
         salf.render_backward(scene, fl, {"depth": g_l}, o=ol, d=dl, d_geo=d_geo, **opts)
-        scene.geo.sub_(lr * d_geo)
-        scene.rgb.sub_(lr * d_rgb)
+        scene.geo.add_(d_geo, alpha=-lr)
+        scene.rgb.add_(d_rgb, alpha=-lr)
         scene.refresh()
         return fc, fl
 
@@ -376,8 +376,8 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
         g_c = (2.0 / (3 * n_cam)) * (fc["rgb"] - tgt_c)
         salf.render_backward(scene, fc, {"rgb": g_c}, o=oc, d=dc, d_geo=d_geo, d_rgb=d_rgb, **opts)
         main.wait_stream(side)
-        scene.geo.sub_(lr * d_geo)
-        scene.rgb.sub_(lr * d_rgb)
+        scene.geo.add_(d_geo, alpha=-lr)
+        scene.rgb.add_(d_rgb, alpha=-lr)
         scene.refresh()
         return fc, fl
 
