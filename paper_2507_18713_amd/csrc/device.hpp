@@ -240,6 +240,33 @@ __device__ __forceinline__ void segment_frame(const SceneView& s, const RayFrame
   sc = __builtin_amdgcn_rcpf((float)h.size);  // exact: size is a power of two
 }
 
+// The ray's own FP64 terms of segment_frame, (o - org) gs and d gs per axis, formed once per ray
+// with the same operations and kept (in LDS) at seg[a * stride] and seg[(3 + a) * stride]:
+// segment_frame_of then takes the same values per hit, so its results are the same bits, with
+// a third of the FP64 instructions (half-rate on the VALU) per hit.
+__device__ __forceinline__ void segment_ray_terms(const SceneView& s, const RayFrame& f, double* seg, int stride) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    seg[a * stride] = ((double)f.o[a] - s.org[a]) * s.gs;
+    seg[(3 + a) * stride] = (double)f.d[a] * s.gs;
+  }
+}
+
+__device__ __forceinline__ void segment_frame_of(const double* seg, int stride, const Hit& h, double rS,
+                                                 float rel[3], float stp[3], float& delta, float& sc) {
+  const double ti = (double)h.t_in;
+  const double dtS = ((double)h.t_out - ti) * rS;
+  delta = (float)dtS;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ogd = seg[a * stride];
+    const double dgd = seg[(3 + a) * stride];
+    rel[a] = (float)fma(ti, dgd, ogd - (double)h.lo[a]);
+    stp[a] = (float)(dtS * dgd);
+  }
+  sc = __builtin_amdgcn_rcpf((float)h.size);
+}
+
 // Unit-cube coordinate of sample k (midpoint k + 1/2) along one axis, clamped to [0, 1].
 __device__ __forceinline__ float sample_u(float rel, float stp, float fk, float sc) {
   return __builtin_amdgcn_fmed3f(fmaf(fk, stp, rel) * sc, 0.0f, 1.0f);

@@ -78,12 +78,13 @@ __device__ __forceinline__ int64_t scheduled_tile(const RenderParams& p, int64_t
 // in scalar registers through it: those are short in the walk, and every extra value there is
 // spilled and reloaded inside its loops.
 template <int FIELD, bool RGB, bool INT, bool p_is_kernarg = false, bool HITS = false>
-__device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk,
-                                            int stk_stride = kThreads) {
+__device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave, int32_t* stk, double* seg,
+                                            int stride = kThreads) {
   int64_t ray;
   float d[3];
   RayFrame f;
   if (!lane_ray(p, wave, threadIdx.x & 63, ray, d, f)) return;
+  if (f.valid) segment_ray_terms(p.scene, f, seg, stride);
   float sh[4] = {kShC0, kShC1 * d[0], kShC1 * d[1], kShC1 * d[2]};
   Accum acc;
   acc.T = 1.0f;
@@ -94,7 +95,7 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
   const double rS = 1.0 / S;
   const float t_min = p.t_min;
   bool cut = false;
-  traverse(p.scene, f, stk, stk_stride, [&](const Hit& h) -> bool {
+  traverse(p.scene, f, stk, stride, [&](const Hit& h) -> bool {
     // every visited voxel is shaded, so the hit's index is the count before shading; stored before
     // the shading, whose arithmetic then covers the stores' latency (the next step's loads would
     // otherwise wait for them)
@@ -104,7 +105,7 @@ __device__ __forceinline__ void render_wave(const RenderParams& p, int64_t wave,
       p.out.hit_voxel[at] = h.voxel;
       reinterpret_cast<float2*>(p.out.hit_t)[at] = make_float2(h.t_in, h.t_out);
     }
-    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc);
+    return shade_voxel<FIELD, RGB, INT>(p.scene, f, sh, h, S, rS, t_min, acc, seg, stride);
   }, [&] { cut = true; });
   const RenderParams* q = &p;
   if (p_is_kernarg) {
@@ -139,8 +140,10 @@ constexpr int kRenderThreads = 64;
 template <int FIELD, bool RGB, bool INT, bool HITS>
 __global__ __launch_bounds__(kRenderThreads) SALF_RENDER_OCCUPANCY void render_kernel(RenderParams p) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kRenderThreads];
+  __shared__ double seg[6 * kRenderThreads];
   const int64_t w = blockIdx.x;
-  render_wave<FIELD, RGB, INT, true, HITS>(p, scheduled_tile(p, w), stk + threadIdx.x, kRenderThreads);
+  render_wave<FIELD, RGB, INT, true, HITS>(p, scheduled_tile(p, w), stk + threadIdx.x, seg + threadIdx.x,
+                                           kRenderThreads);
 }
 
 // ---- one ray in pieces
@@ -524,6 +527,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MASK =
                                                                 int64_t n_tiles, uint32_t* counter,
                                                                 const int32_t* sched) {
   __shared__ int32_t stk[SALF_MAX_LEVEL * kThreads];
+  __shared__ double seg[6 * kThreads];
   const int lane = threadIdx.x & 63;
   const bool ordered = sched != nullptr && sched[0] == (int32_t)n_tiles;
   for (;;) {
@@ -539,14 +543,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MASK =
     const BatchItem& b = items[find_item(items, n_items, tile)];
     const int64_t w = tile - b.tile_begin;
     const int v = b.variant;
-    if constexpr ((MASK & 0x01u) != 0) if (v == 0) render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x02u) != 0) if (v == 1) render_wave<SALF_FIELD_CORNER, true, false>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x04u) != 0) if (v == 2) render_wave<SALF_FIELD_CORNER, false, true>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x08u) != 0) if (v == 3) render_wave<SALF_FIELD_CORNER, true, true>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x10u) != 0) if (v == 4) render_wave<kFieldCornerActivated, false, false>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x20u) != 0) if (v == 5) render_wave<kFieldCornerActivated, true, false>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x40u) != 0) if (v == 6) render_wave<kFieldCornerActivated, false, true>(b.p, w, stk + threadIdx.x);
-    if constexpr ((MASK & 0x80u) != 0) if (v == 7) render_wave<kFieldCornerActivated, true, true>(b.p, w, stk + threadIdx.x);
+    if constexpr ((MASK & 0x01u) != 0) if (v == 0) render_wave<SALF_FIELD_CORNER, false, false>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x02u) != 0) if (v == 1) render_wave<SALF_FIELD_CORNER, true, false>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x04u) != 0) if (v == 2) render_wave<SALF_FIELD_CORNER, false, true>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x08u) != 0) if (v == 3) render_wave<SALF_FIELD_CORNER, true, true>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x10u) != 0) if (v == 4) render_wave<kFieldCornerActivated, false, false>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x20u) != 0) if (v == 5) render_wave<kFieldCornerActivated, true, false>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x40u) != 0) if (v == 6) render_wave<kFieldCornerActivated, false, true>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
+    if constexpr ((MASK & 0x80u) != 0) if (v == 7) render_wave<kFieldCornerActivated, true, true>(b.p, w, stk + threadIdx.x, seg + threadIdx.x);
   }
 }
 

@@ -27,7 +27,8 @@ __device__ __forceinline__ float sdf_sigma(float q, float ha, float ib) {
 template <int FIELD, bool RGB, bool INT>
 __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
                                            int S, double rS, float t_min, Accum& acc, const float* geo_row,
-                                           const float* rgb_row, const float* int_row) {
+                                           const float* rgb_row, const float* int_row,
+                                           const double* seg = nullptr, int seg_stride = 0) {
   const float ti = h.t_in;
   float g[8], c[3][8], it[8];
   {
@@ -81,7 +82,8 @@ __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f
   }
 
   float rel[3], stp[3], delta, sc;
-  segment_frame(s, f, h, rS, rel, stp, delta, sc);
+  if (seg) segment_frame_of(seg, seg_stride, h, rS, rel, stp, delta, sc);
+  else segment_frame(s, f, h, rS, rel, stp, delta, sc);
 
   if (!kAffine) {
     // Corner fields: colour and intensity are linear in the corner values, so the voxel's share
@@ -153,14 +155,15 @@ __device__ __forceinline__ bool shade_rows(const SceneView& s, const RayFrame& f
 // corner scenes); coalescing across lanes comes from coherent rays.
 template <int FIELD, bool RGB, bool INT>
 __device__ __forceinline__ bool shade_voxel(const SceneView& s, const RayFrame& f, const float sh[4], const Hit& h,
-                                            int S, double rS, float t_min, Accum& acc) {
+                                            int S, double rS, float t_min, Accum& acc,
+                                            const double* seg = nullptr, int seg_stride = 0) {
   const int64_t v = h.voxel;
   constexpr bool kAct = FIELD == kFieldCornerActivated;
   const float* geo = kAct ? s.act_geo : s.geo;
   const float* rgb = kAct ? s.act_rgb : s.rgb;
   const float* itn = kAct ? s.act_int : s.inten;
   return shade_rows<FIELD, RGB, INT>(s, f, sh, h, S, rS, t_min, acc, geo + v * 8, RGB ? rgb + v * 24 : nullptr,
-                                     INT ? itn + v * 8 : nullptr);
+                                     INT ? itn + v * 8 : nullptr, seg, seg_stride);
 }
 
 }  // namespace salf
