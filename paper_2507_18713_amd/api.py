@@ -561,7 +561,8 @@ class RenderFunction(torch.autograd.Function):
     """Differentiable render (corner or paper field).  apply(geo, rgb, intensity, scene, sensor, o, d, opts) ->
     (rgb, depth, opacity, intensity); geo/rgb/intensity must be the scene's own parameter
     tensors (the render reads them in place).  rgb/intensity outputs are empty tensors when the
-    scene lacks that parameter."""
+    scene lacks that parameter.  opts may hold hit_capacity > 0: the forward then stores up to that
+    many hits per ray and the backward reads them instead of walking the scene again."""
 
     @staticmethod
     def forward(ctx, geo, rgb, intensity, scene: Scene, sensor, o, d, opts: dict):
@@ -570,21 +571,26 @@ class RenderFunction(torch.autograd.Function):
             want.append("rgb")
         if intensity is not None:
             want.append("intensity")
-        res = render(scene, sensor=sensor, o=o, d=d, outputs=want, **opts)
-        ctx.scene, ctx.sensor, ctx.o, ctx.d, ctx.opts = scene, sensor, o, d, opts
+        cap = int(opts.get("hit_capacity", 0))
+        ropts = {k: v for k, v in opts.items() if k != "hit_capacity"}
+        res = render(scene, sensor=sensor, o=o, d=d, outputs=want, hit_capacity=cap, **ropts)
+        ctx.scene, ctx.sensor, ctx.o, ctx.d, ctx.opts = scene, sensor, o, d, ropts
         empty = torch.empty(0, device=geo.device)
         outs = (res.get("rgb", empty), res["depth"], res["opacity"], res.get("intensity", empty))
+        hits = (res["hit_voxel"], res["hit_t"]) if cap > 0 else (empty, empty)
         # the backward reads the parameters in place and the forward's outputs (its suffix sums are
         # formed from them), so both go through autograd's saved-tensor version checks: an in-place
         # change of either before backward raises instead of corrupting the gradient
-        ctx.save_for_backward(geo, rgb, intensity, *outs, res["t_end"], res["n_hits"])
+        ctx.save_for_backward(geo, rgb, intensity, *outs, res["t_end"], res["n_hits"], *hits)
         return outs
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_opacity, g_int):
         sc = ctx.scene
-        _, _, _, o_rgb, o_depth, o_opacity, o_int, t_end, n_hits = ctx.saved_tensors
+        _, _, _, o_rgb, o_depth, o_opacity, o_int, t_end, n_hits, hit_voxel, hit_t = ctx.saved_tensors
         saved = {"depth": o_depth, "opacity": o_opacity, "t_end": t_end, "n_hits": n_hits}
+        if hit_voxel.numel():
+            saved["hit_voxel"], saved["hit_t"] = hit_voxel, hit_t
         if o_rgb.numel():
             saved["rgb"] = o_rgb
         if o_int.numel():

@@ -304,6 +304,17 @@ def test_autograd_function(salf):
     assert torch.allclose(dg, scene.geo.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(dr, scene.rgb.grad, rtol=1e-4, atol=1e-6)
     assert torch.allclose(di, scene.intensity.grad, rtol=1e-4, atol=1e-6)
+    # with stored hits (2 per ray: most rays are walked for the rest) the same gradient
+    g_walk = [t.grad.clone() for t in (scene.geo, scene.rgb, scene.intensity)]
+    for t in (scene.geo, scene.rgb, scene.intensity):
+        t.grad = None
+    for cap in (2, 64):
+        rgb, depth, op, inten = salf.RenderFunction.apply(scene.geo, scene.rgb, scene.intensity, scene, None,
+                                                          to_dev(o), to_dev(d), dict(opts, hit_capacity=cap))
+        ((rgb ** 2).sum() + depth.abs().sum() + inten.sum()).backward()
+        for t, ref in zip((scene.geo, scene.rgb, scene.intensity), g_walk):
+            assert torch.allclose(t.grad, ref, rtol=1e-4, atol=1e-6), cap
+            t.grad = None
     # the backward reads the returned outputs: changing one in place before backward is an error,
     # not a silently wrong gradient
     rgb, depth, op, inten = salf.RenderFunction.apply(scene.geo, scene.rgb, scene.intensity, scene, None,
