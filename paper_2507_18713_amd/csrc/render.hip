@@ -3,8 +3,10 @@
 // intensity and opacity with FP32 transmittance and early termination (Eq. 1-4, Sec. 3.2).
 //
 // Work mapping: one lane per ray.  In sensor mode a wave64 covers a tile of 64 neighbouring rays
-// (16x4 pixels of a pinhole camera, 8x8 of a fisheye, 32 columns x 2 beams of a LiDAR) so that the lanes of a wave walk nearby voxels and
-// share their parameter cache lines; ray generation is fused (no ray buffer in HBM).
+// (16x4 pixels of a pinhole camera, 8x8 of a fisheye, 32 columns x 2 beams of a LiDAR) so that
+// the lanes of a wave walk nearby voxels and share their parameter cache lines; ray generation is
+// fused (no ray buffer in HBM).  The per-tile render kernels run one wave per workgroup; the
+// backward and the persistent serving kernel run four.
 #include <string.h>
 
 #include <atomic>
