@@ -315,12 +315,13 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
         oc.append(r["o"])
         dc.append(r["d"])
     oc, dc = torch.cat(oc), torch.cat(dc)
-    # the sampled pixels are batched in 8x8 screen tiles (ray bundles), so that the rays of one
-    # wave see neighbouring voxels as in a frame render
+    # the sampled pixels are batched in 16x16 screen blocks (ray bundles; at 5% of the pixels a wave's
+    # 64 rays cover about one block), so that the rays of one wave see neighbouring voxels as in a
+    # frame render (8x8 blocks: forward and backward ~2-4% slower)
     ic = np.sort(rng.choice(oc.shape[0], n_cam, replace=False))
     view, pix = ic // (1920 * 1080), ic % (1920 * 1080)
     py, px = pix // 1920, pix % 1920
-    ic = ic[np.lexsort((px % 8, py % 8, px // 8, py // 8, view))]
+    ic = ic[np.lexsort((px % 16, py % 16, px // 16, py // 16, view))]
     ic = torch.from_numpy(ic).to(dev)
     ol, dl = [], []
     for x in (-60.0, 20.0):
@@ -422,7 +423,7 @@ def training_bench(salf, torch, dev, data, steps=10, seed=4):
     paper = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps)
     sdf = paper_field_pass(salf, torch, dev, data, oc, dc, ol, dl, g_c, g_l, opts, steps, field="sdf")
     return {"workload": "driving scene, 838,861 camera pixels (8 random views) + 209,715 LiDAR rays (2 sweeps), "
-                        "batched in 8x8 pixel / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
+                        "batched in 16x16 pixel blocks / 32x2 LiDAR tiles, L2 colour + L1 depth vs a perturbed copy, "
                         "SGD update + activation refresh in the step; the forwards store each ray's hits "
                         f"(up to {HIT_CAPACITY}) and the backwards read them; the LiDAR batch on a second stream",
             "rays": n_cam + n_lid, "ms_per_step_median": round(ms, 3),
